@@ -1,0 +1,211 @@
+"""Benchmark: objective+gradient evaluations of the 4-qubit multiple-shooting problem on one MI355X.
+
+One step = one full evaluation of the hot path on the 4-qubit system
+(q=4, L=4, N=256, E=16, N_T=100000 steps, M=128 windows, 60 splines x 3 carriers
+per qubit, d=1440 controls, 1,040,384 window-state variables): control table,
+forward sweep of every window, FP64 boundary reductions, backward adjoint
+sweep, gradient projection onto the controls and the window-state gradient.
+Inputs (controls, window states = GPU roll-out + seeded noise) are resident in
+HBM before the timed region; outputs stay on the device.
+
+Prints ONE JSON line (rank 0).  --gpus > 1 is rejected: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VECTOR_TFLOPS = 157.3      # MI355X published FP32 vector peak (packed)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (packed FP32 is not used)
+PEAK_FP64_VECTOR_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_flops(w, kit):
+    """Useful flops of one forward and one backward launch (measurement)."""
+    q, L = w.q, w.L
+    ladder = 16.0 * q * (L - 1) / L          # complex MACs of the nonzero ladder terms, per entry
+    per_iter = ladder + 8.0                  # + z = x -/+ i D^-1 S
+    fwd = kit * per_iter + 10.0              # + D^-1 u and u' = 2z - u
+    bwd = 2.0 * fwd + ladder                 # two right-hand sides + the per-step inner products
+    units = float(w.N) * w.E * w.n_steps     # entry-steps per sweep
+    return fwd * units, bwd * units
+
+
+def percentile(xs, p):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * p / 100.0
+    lo, hi = math.floor(k), math.ceil(k)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def cpu_baseline(w, alpha, seconds):
+    """The FP64 CPU oracle timed on a bounded sample of the same workload: the forward and
+    adjoint work of the first nw windows (all columns), scaled to one whole evaluation."""
+    from oracle import oracle
+    from paper_2407_13950_amd import workloads as WL
+    W = WL.gen_qr_states(w, 7)            # timing only; the oracle's cost does not depend on W's values
+    t0 = time.perf_counter()
+    oracle.windows(w, alpha, W, 1, 1)
+    t1 = time.perf_counter() - t0
+    nw = int(max(1, min(w.n_windows, round(seconds / max(t1, 1e-3)))))
+    log(f"cpu baseline: one window {t1:.2f} s; timing {nw} windows")
+    t0 = time.perf_counter()
+    oracle.windows(w, alpha, W, 1, nw)
+    t = time.perf_counter() - t0
+    per_eval = t * w.n_windows / nw
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 1.0 / per_eval, "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"{nw} of {w.n_windows} windows x {w.E} columns (forward + adjoint), "
+                      f"{t:.1f} s, scaled by {w.n_windows}/{nw}",
+            "seconds_per_eval": per_eval}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--fp64-steps", type=int, default=3, help="steps of the plain FP64 form timed for comparison")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU-oracle sample size (0: skip)")
+    ap.add_argument("--seed", type=int, default=2024)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU sharding is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2407_13950_amd import qoc, workloads as WL
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    w = WL.c3()
+    alpha_np = WL.gen_alpha(w, args.seed)
+    alpha = torch.tensor(alpha_np, device=dev)
+
+    def make(precision):
+        s = qoc.System(w, precision=precision)
+        s.set_controls(alpha)
+        return s
+
+    log(f"workload {w.name}: N={w.N} E={w.E} N_T={w.n_steps} M={w.n_windows} d={w.d}")
+    s = make(args.precision)
+    t0 = time.perf_counter()
+    Wt, _ = s.rollout(device=True)
+    noise = torch.tensor(WL.gen_noise(w, args.seed), device=dev)
+    W = (Wt + noise).contiguous()
+    s.set_window_states(W)
+    torch.cuda.synchronize()
+    log(f"roll-out for the window states: {time.perf_counter() - t0:.2f} s")
+
+    P = torch.empty(1, dtype=torch.float64, device=dev)
+    terms = torch.empty(4 + w.n_windows, dtype=torch.float64, device=dev)
+    ga = torch.empty(w.d, dtype=torch.float64, device=dev)
+    gW = torch.empty((w.n_windows - 1, w.E, w.N), dtype=torch.complex128, device=dev)
+
+    for i in range(args.warmup):
+        s.gradient_into(P, terms, ga, gW)
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    s.synchronize()     # raises if the fixed-point bound was violated
+
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    s.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        s.gradient_into(P, terms, ga, gW)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tm = s.timings()
+    lat = [a.elapsed_time(b) for a, b in ev]
+    s.synchronize()
+    log(f"timed {args.steps} steps: {elapsed:.3f} s; phases(ms) "
+        + ", ".join(f"{k}={tm[k]:.3f}" for k in qoc.PHASES))
+
+    kit = tm["fixed_point_iters"]
+    f_fwd, f_bwd = algorithmic_flops(w, kit)
+    dominant = "backward" if tm["backward"] >= tm["forward"] else "forward"
+    flops = f_bwd if dominant == "backward" else f_fwd
+    achieved = flops / (tm[dominant] * 1e-3) / 1e12
+    value = args.steps / elapsed
+    result = {
+        "metric": "objective+gradient evals/s at 4 qubits",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"4-qubit QFT-shaped system q=4 L=4 N=256 E=16 N_T={w.n_steps} M={w.n_windows} "
+                               f"d={w.d} window-state vars={2 * w.n_w}",
+                   "propagation": args.precision, "reductions": "f64", "fixed_point_iters": kit,
+                   "checkpoint_every": w.checkpoint_every},
+        "window_steps_per_s": value * 2 * w.n_steps,
+        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
+        "phases_ms": {k: tm[k] for k in qoc.PHASES},
+        "roofline": {"kernel": f"k_backward<{'float' if args.precision == 'fp32' else 'double'},4,4,3>"
+                     if dominant == "backward" else "k_forward",
+                     "bound": "alu", "achieved": achieved,
+                     "peak": PEAK_FP32_VECTOR_TFLOPS if args.precision == "fp32" else PEAK_FP64_VECTOR_TFLOPS,
+                     "unit": "TFLOP/s",
+                     "frac": achieved / (PEAK_FP32_VECTOR_TFLOPS if args.precision == "fp32" else PEAK_FP64_VECTOR_TFLOPS),
+                     "traffic": None,
+                     "peak_without_packed_fp32": PEAK_FP32_NONPACKED_TFLOPS,
+                     "flops_per_launch": flops, "mean_launch_ms": tm[dominant]},
+        "P": float(P.item()),
+    }
+    s.close()
+
+    if args.fp64_steps > 0 and args.precision == "fp32":
+        s64 = make("fp64")
+        s64.set_window_states(W)
+        s64.gradient_into(P, terms, ga, gW)
+        torch.cuda.synchronize()
+        s64.enable_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(args.fp64_steps):
+            s64.gradient_into(P, terms, ga, gW)
+        torch.cuda.synchronize()
+        e64 = time.perf_counter() - t0
+        t64 = s64.timings()
+        result["fp64_plain"] = {"value": args.fp64_steps / e64, "unit": "evals/s", "steps": args.fp64_steps,
+                                "fixed_point_iters": t64["fixed_point_iters"],
+                                "phases_ms": {k: t64[k] for k in qoc.PHASES}}
+        s64.close()
+        log(f"fp64 plain form: {args.fp64_steps / e64:.2f} evals/s")
+
+    if args.cpu_seconds > 0:
+        result["cpu_baseline"] = cpu_baseline(w, alpha_np, args.cpu_seconds)
+        log(f"cpu baseline: {result['cpu_baseline']['value']:.4f} evals/s")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

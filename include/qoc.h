@@ -1,0 +1,182 @@
+/*
+ * qoc.h -- C ABI of the MI355X library for the multiple-shooting quantum
+ * optimal-control objective and its adjoint gradient (arxiv 2407.13950).
+ *
+ * The calls follow the paper's problem statement (Sec. 3): build the system,
+ * set the controls alpha and the window initial states W^1..W^{M-1}, evaluate
+ * the penalty objective P (eq. penalty-fcn), evaluate its gradient with respect
+ * to alpha (eq. grad-int, exact in the time-discrete setting) and to the real
+ * and imaginary parts of every W^m (eq. dP-dW with the factor 2 of App. B).
+ *
+ * Conventions shared by every call
+ *   - Return value: QOC_OK (0) or a negative QOC_E* code; qoc_last_error()
+ *     gives a message for the calling thread.  No exception crosses the ABI.
+ *   - Ownership: the caller owns every buffer it passes.  Inputs are copied
+ *     (asynchronously, on the context's stream) before the call returns or
+ *     before any later work on that stream; the library keeps no caller pointer.
+ *   - Memory kind: each buffer argument comes with a QOC_HOST or QOC_DEVICE flag.
+ *     Device pointers must be HIP device (or managed) allocations of the
+ *     context's device.  Host outputs make the call synchronous; device outputs
+ *     are written on the context's stream and the call returns without waiting.
+ *   - Layouts: complex numbers are interleaved (re, im) doubles.  A state
+ *     matrix is N x E, column-major (column c occupies entries c*N .. c*N+N-1),
+ *     N = L^q levels, E = 2^q essential states.  Rows enumerate the tensor-
+ *     product basis with qubit 0 as the most significant digit; essential state
+ *     e sits at the row whose levels are the binary digits of e.
+ *   - A context is not thread-safe; use one context per optimisation run or
+ *     serialise calls.  Distinct contexts may be used from distinct threads.
+ */
+#ifndef QOC_H
+#define QOC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QOC_OK 0
+#define QOC_EINVAL (-1)       /* invalid argument, shape or non-finite input      */
+#define QOC_ENOMEM (-2)       /* device allocation failed                          */
+#define QOC_EDEVICE (-3)      /* HIP runtime or kernel launch error                 */
+#define QOC_ENOTCONV (-4)     /* fixed-point solve cannot meet its tolerance        */
+#define QOC_EUNSUPPORTED (-5) /* no kernel instance for this (qubits, levels) pair  */
+#define QOC_ESTATE (-6)       /* call out of order (e.g. gradient before controls)  */
+
+#define QOC_HOST 0
+#define QOC_DEVICE 1
+
+/* Propagation precision.  Reductions (penalty, infidelity) and the gradient
+ * accumulation are FP64 in both modes. */
+#define QOC_FP64 0   /* states and adjoints propagated in double                 */
+#define QOC_FP32 1   /* states and adjoints propagated in float (complex FP32)   */
+
+typedef struct qoc_ctx qoc_ctx;
+
+/* System description (copied by qoc_create).
+ *
+ * Hamiltonian (Sec. 2, eqs. sys-ham and ctrl-ham, with a diagonal drift):
+ *   H(t) = H_d + sum_j [ 2 pi d_j(t) a_j + conj(2 pi d_j(t)) a_j^+ ],
+ *   H_d  = sum_j [ detuning_j l_j + anharmonicity_j/2 l_j (l_j - 1) ]
+ *        + sum_{j<q-1} cross_kerr_j l_j l_{j+1}             (rad/ns),
+ * a_j the lowering operator of qubit j truncated to n_levels levels.
+ * Controls (eq. dj-ctrl and the B-spline expansion of Sec. 2):
+ *   d_j(t) = sum_f exp(i carrier_freq[j*n_carriers+f] t) sum_s (alpha1_jfs + i alpha2_jfs) B_s(t)
+ * with quadratic cardinal B-splines B_s(t) = B(t/dtau + 1/2 - s), dtau = T/(n_splines-2),
+ * s = 0..n_splines-1 (alpha in GHz, t in ns).  alpha is indexed
+ * ((j*n_carriers + f)*2 + part)*n_splines + s, part 0 = alpha1, part 1 = alpha2.
+ * Time stepping: n_steps implicit-midpoint steps of dt = T/n_steps with H at the
+ * step midpoint (Sec. 5); window m = 1..M covers steps floor((m-1) n_steps/M) ..
+ * floor(m n_steps/M) - 1 (equal durations up to one step, Sec. 3).
+ * Objective (eqs. mod-infid, penalty-fcn), n replaced by E:
+ *   P = |U^M|_F^2/E - |<V, U^M>_F|^2/E^2 + mu/2 sum_{m<M} |U^m(t_m) - W^m|_F^2. */
+typedef struct qoc_system_desc {
+  int32_t n_qubits;             /* q, 1..6                                            */
+  int32_t n_levels;             /* L >= 2 levels per qubit (guard levels included)    */
+  const double *detuning;       /* [q] rad/ns, host                                   */
+  const double *anharmonicity;  /* [q] rad/ns, host                                   */
+  const double *cross_kerr;     /* [q-1] rad/ns, host; NULL = 0                       */
+  int32_t n_carriers;           /* carriers per qubit, >= 1                           */
+  const double *carrier_freq;   /* [q*n_carriers] rad/ns, host                        */
+  int32_t n_splines;            /* B-spline coefficients per carrier, >= 3            */
+  double T;                     /* gate duration in ns, > 0                           */
+  int64_t n_steps;              /* N_T >= n_windows                                   */
+  int32_t n_windows;            /* M >= 1                                             */
+  double mu;                    /* penalty coefficient, >= 0                          */
+  const double *target;         /* [2*E*E] unitary E x E target, column-major, host   */
+  int32_t precision;            /* QOC_FP64 or QOC_FP32                               */
+  int32_t fixed_point_iters;    /* 0: derived per evaluation from a contraction bound */
+  double solve_tol;             /* per-step fixed-point error target; 0: default      */
+  int32_t checkpoint_every;     /* >0: store states every this many steps per window
+                                   and re-sync the reverse reconstruction there; 0: none */
+  int32_t device;               /* HIP device ordinal                                 */
+} qoc_system_desc;
+
+/* Read-only facts about a context. */
+typedef struct qoc_info {
+  int32_t N, E, d;              /* levels, essential states, control count            */
+  int32_t n_windows;
+  int64_t n_window_doubles;     /* 2*(M-1)*N*E: doubles in W and grad_W               */
+  int32_t n_terms;              /* 4 + M: doubles written to `terms`                  */
+  int32_t lane_digits;          /* register layout: qubits spread over lanes          */
+  int32_t columns_per_wave;
+  int64_t device_bytes;         /* device memory held by the context                  */
+} qoc_info;
+
+/* Build the system on `desc->device`, allocate its device buffers.  Ownership
+ * of *out passes to the caller (release with qoc_destroy).  Errors: QOC_EINVAL
+ * (bad sizes, non-finite parameters, non-unitary target), QOC_EUNSUPPORTED,
+ * QOC_ENOMEM, QOC_EDEVICE. */
+int qoc_create(const qoc_system_desc *desc, qoc_ctx **out);
+int qoc_destroy(qoc_ctx *ctx);
+int qoc_get_info(const qoc_ctx *ctx, qoc_info *out);
+
+/* Stream for all later work of this context (a hipStream_t; NULL = the null
+ * stream).  The caller keeps the stream alive while the context uses it. */
+int qoc_set_stream(qoc_ctx *ctx, void *hip_stream);
+
+/* Controls alpha [d] (eq. dj-ctrl and the B-spline expansion).  Copied. */
+int qoc_set_controls(qoc_ctx *ctx, const double *alpha, int64_t d, int32_t where);
+
+/* Window initial states W^1..W^{M-1}: n_doubles = 2*(M-1)*N*E doubles, window-
+ * major, each a column-major N x E complex matrix (eqs. sch-ic, con0).  W^0 = I
+ * (the essential columns of the identity) is implied.  Copied.  With M = 1 pass
+ * n_doubles = 0. */
+int qoc_set_window_states(qoc_ctx *ctx, const double *W, int64_t n_doubles, int32_t where);
+
+/* Objective P (eq. penalty-fcn).  P: 1 double; terms (nullable): 4 + M doubles
+ *   [J_V(U^M), mu/2 sum |C^m|^2, |U^M|_F^2, Re gamma, Im gamma, |C^1|_F^2 .. |C^{M-1}|_F^2]
+ * with C^m = U^m(t_m) - W^m (eq. constraint) and gamma = <V, U^M>_F.  Requires
+ * controls and (for M > 1) window states.  QOC_ENOTCONV (host outputs only)
+ * when the contraction bound of the implicit solve exceeded its limit. */
+int qoc_objective(qoc_ctx *ctx, double *P, double *terms, int32_t where);
+
+/* Objective and gradient in one call (forward sweep, FP64 boundary reductions,
+ * backward adjoint sweep; Sec. 3.1).  grad_alpha: d doubles, dP/dalpha
+ * (eq. grad-int, exact for the discrete scheme).  grad_W: 2*(M-1)*N*E doubles in
+ * the layout of W; the re slot holds dP/dRe W^m, the im slot dP/dIm W^m
+ * (= mu (W^m - U^m(t_m)) - 2 Lambda^{m+1}(t_m), App. B).  All outputs share `where`.
+ * P, terms and grad_W may be NULL. */
+int qoc_gradient(qoc_ctx *ctx, double *P, double *terms, double *grad_alpha, double *grad_W, int32_t where);
+
+/* Adjoint sweep only (Sec. 3.1): dP/dalpha and dP/dW for the controls and
+ * window states of the most recent successful qoc_objective call on this
+ * context, reusing its forward sweep.  QOC_ESTATE when no objective has been
+ * evaluated since the last qoc_set_controls / qoc_set_window_states.  Outputs
+ * as in qoc_gradient. */
+int qoc_backward(qoc_ctx *ctx, double *grad_alpha, double *grad_W, int32_t where);
+
+/* Roll-out (Sec. 3.2): one propagation over [0, T] from W^0 = I under the
+ * current controls.  W_out (nullable): the states at t_1..t_{M-1} in the layout
+ * of W; U_out (nullable): U(T), 2*N*E doubles.  Both share `where`. */
+int qoc_rollout(qoc_ctx *ctx, double *W_out, double *U_out, int32_t where);
+
+/* Per-phase kernel timing with HIP events recorded on the context's stream.
+ * Phases: 0 controls (+ iteration count), 1 forward sweep, 2 boundary reductions,
+ * 3 backward (adjoint) sweep, 4 gradient series reduction + B-spline projection,
+ * 5 window-state gradient; 6 = whole evaluation.  qoc_enable_timing(ctx, 1)
+ * starts a fresh record (up to 4096 evaluations are kept; later ones are not
+ * timed); qoc_get_timings synchronises the stream and returns the mean duration
+ * per phase over the recorded calls that ran it (qoc_objective runs phases
+ * 0-2, qoc_backward 3-5, qoc_gradient 0-5; "whole evaluation" is each call's span). */
+typedef struct qoc_timings {
+  int32_t n_calls;              /* evaluations recorded                              */
+  int32_t n_grad_calls;         /* of which gradient evaluations                     */
+  double mean_ms[8];            /* mean kernel time per phase, ms                    */
+  int32_t fixed_point_iters;    /* iteration count used by the last evaluation       */
+} qoc_timings;
+int qoc_enable_timing(qoc_ctx *ctx, int32_t on);
+int qoc_get_timings(qoc_ctx *ctx, qoc_timings *out);
+
+/* Block until this context's queued work is done; returns QOC_ENOTCONV if a
+ * previous evaluation flagged a fixed-point bound violation (then clears it). */
+int qoc_synchronize(qoc_ctx *ctx);
+
+/* Message for the last failing call on this thread (never NULL). */
+const char *qoc_last_error(void);
+const char *qoc_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QOC_H */

@@ -1,0 +1,460 @@
+// C ABI of the multiple-shooting objective/gradient library: validation,
+// system build (host, FP64, once per context), device buffers, and the kernel
+// sequences of qoc_kernels.hip.
+#include "../../include/qoc.h"
+#include "qoc_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+int fail(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(QOC_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_OR_RETURN(expr)                          \
+  do {                                               \
+    hipError_t e_ = (expr);                          \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+  } while (0)
+
+bool finite_all(const double *p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+// Largest eigenvalue of a + a^+ on L levels: the symmetric tridiagonal matrix
+// with zero diagonal and off-diagonal sqrt(1..L-1), by Sturm-sequence bisection.
+double ladder_norm(int L) {
+  auto count_below = [L](double x) {
+    int cnt = 0;
+    double d = -x;
+    for (int i = 0; i < L; ++i) {
+      if (i > 0) d = -x - (double)i / (d == 0.0 ? 1e-300 : d);
+      if (d < 0) ++cnt;
+    }
+    return cnt;
+  };
+  double lo = 0.0, hi = 2.0 * std::sqrt((double)(L - 1)) + 1.0;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) == L) hi = mid; else lo = mid;
+  }
+  return hi;
+}
+
+}  // namespace
+
+struct qoc_ctx {
+  int q = 0, L = 0, N = 0, E = 0, nf = 0, d1 = 0, M = 0, d = 0;
+  long long NT = 0;
+  int device = 0;
+  int fp64 = 0;
+  hipStream_t stream = nullptr;
+  bool have_alpha = false, have_W = false;
+  bool forward_valid = false;                      // forward sweep matches the current inputs
+  size_t bytes = 0;
+  std::vector<void *> allocs;
+  double *roll_W = nullptr, *roll_U = nullptr;   // staging for host roll-out outputs
+  qoc::DevSys dev{};
+  // timing: per recorded evaluation, events at the phase boundaries
+  static constexpr int kTimedCalls = 4096;
+  bool timing = false;
+  std::vector<hipEvent_t> events;                  // kTimedCalls * (N_PHASES + 1)
+  std::vector<char> call_ph0, call_ph1;           // phases [ph0, ph1) run by each recorded call
+  int n_timed = 0;
+
+  template <typename P>
+  int alloc(P **p, size_t bytes_) {
+    void *v = nullptr;
+    hipError_t e = hipMalloc(&v, std::max<size_t>(bytes_, 16));
+    if (e != hipSuccess) return fail(QOC_ENOMEM, std::string("hipMalloc of ") + std::to_string(bytes_) + " bytes failed");
+    allocs.push_back(v);
+    bytes += bytes_;
+    *p = reinterpret_cast<P *>(v);
+    return QOC_OK;
+  }
+  ~qoc_ctx() {
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    for (void *p : allocs) (void)hipFree(p);
+  }
+  hipEvent_t ev(int call, int k) { return events[(size_t)call * (qoc::N_PHASES + 1) + k]; }
+};
+
+extern "C" {
+
+const char *qoc_last_error(void) { return g_last_error.c_str(); }
+
+const char *qoc_strerror(int code) {
+  switch (code) {
+    case QOC_OK: return "ok";
+    case QOC_EINVAL: return "invalid argument";
+    case QOC_ENOMEM: return "out of device memory";
+    case QOC_EDEVICE: return "HIP device error";
+    case QOC_ENOTCONV: return "fixed-point solve bound not met";
+    case QOC_EUNSUPPORTED: return "unsupported (qubits, levels) pair";
+    case QOC_ESTATE: return "call out of order";
+    default: return "unknown error";
+  }
+}
+
+int qoc_create(const qoc_system_desc *desc, qoc_ctx **out) {
+  if (!desc || !out) return fail(QOC_EINVAL, "qoc_create: NULL argument");
+  *out = nullptr;
+  const qoc_system_desc &D = *desc;
+  if (D.n_qubits < 1 || D.n_qubits > 6) return fail(QOC_EINVAL, "n_qubits must be in 1..6");
+  if (D.n_levels < 2 || D.n_levels > 8) return fail(QOC_EINVAL, "n_levels must be in 2..8");
+  if (D.n_carriers < 1 || D.n_splines < 3) return fail(QOC_EINVAL, "need n_carriers >= 1 and n_splines >= 3");
+  if (!(D.T > 0.0) || !std::isfinite(D.T)) return fail(QOC_EINVAL, "T must be finite and > 0");
+  if (D.n_windows < 1 || D.n_steps < D.n_windows) return fail(QOC_EINVAL, "need 1 <= n_windows <= n_steps");
+  if (!(D.mu >= 0.0) || !std::isfinite(D.mu)) return fail(QOC_EINVAL, "mu must be finite and >= 0");
+  if (D.precision != QOC_FP64 && D.precision != QOC_FP32) return fail(QOC_EINVAL, "precision must be QOC_FP64 or QOC_FP32");
+  if (D.fixed_point_iters < 0 || D.fixed_point_iters > 64) return fail(QOC_EINVAL, "fixed_point_iters must be in 0..64");
+  if (D.checkpoint_every < 0) return fail(QOC_EINVAL, "checkpoint_every must be >= 0");
+  if (!(D.solve_tol >= 0.0) || !std::isfinite(D.solve_tol)) return fail(QOC_EINVAL, "solve_tol must be finite and >= 0");
+  if (!D.detuning || !D.anharmonicity || !D.carrier_freq || !D.target) return fail(QOC_EINVAL, "NULL system array");
+
+  const int q = D.n_qubits, L = D.n_levels;
+  long long N = 1;
+  for (int j = 0; j < q; ++j) N *= L;
+  const int E = 1 << q;
+  const int nf = D.n_carriers, d1 = D.n_splines, M = D.n_windows;
+  const long long NT = D.n_steps;
+  if (!finite_all(D.detuning, q) || !finite_all(D.anharmonicity, q) || (D.cross_kerr && !finite_all(D.cross_kerr, q - 1)) ||
+      !finite_all(D.carrier_freq, (size_t)q * nf) || !finite_all(D.target, 2 * (size_t)E * E))
+    return fail(QOC_EINVAL, "non-finite system parameter");
+  // the target must be unitary (eq. mod-infid assumes V^+ V = I)
+  {
+    double worst = 0.0;
+    for (int a = 0; a < E; ++a)
+      for (int b = 0; b < E; ++b) {
+        std::complex<double> acc = 0.0;
+        for (int r = 0; r < E; ++r)
+          acc += std::conj(std::complex<double>(D.target[2 * (a * E + r)], D.target[2 * (a * E + r) + 1])) *
+                 std::complex<double>(D.target[2 * (b * E + r)], D.target[2 * (b * E + r) + 1]);
+        worst = std::max(worst, std::abs(acc - (a == b ? 1.0 : 0.0)));
+      }
+    if (worst > 1e-10) return fail(QOC_EINVAL, "target is not unitary");
+  }
+  const int fp64 = D.precision == QOC_FP64;
+  int ld = 0, cpw = 1;
+  if (!qoc::layout_for(q, L, fp64, &ld, &cpw))
+    return fail(QOC_EUNSUPPORTED, "no kernel instance for q=" + std::to_string(q) + " L=" + std::to_string(L));
+
+  HIP_OR_RETURN(hipSetDevice(D.device));
+  qoc_ctx *c = new qoc_ctx();
+  c->q = q; c->L = L; c->N = (int)N; c->E = E; c->nf = nf; c->d1 = d1; c->M = M;
+  c->d = 2 * d1 * q * nf; c->NT = NT; c->device = D.device; c->fp64 = fp64;
+
+  // ---- host system build (FP64)
+  const double dt = D.T / (double)NT;
+  std::vector<long long> kstart(M + 1);
+  for (int m = 0; m <= M; ++m) kstart[m] = (long long)(((__int128)m * NT) / M);
+  long long maxlen = 0;
+  for (int m = 0; m < M; ++m) maxlen = std::max(maxlen, kstart[m + 1] - kstart[m]);
+  std::vector<double> dinv(2 * N);
+  std::vector<long long> stride(q);
+  for (int j = 0; j < q; ++j) { stride[j] = 1; for (int k = j + 1; k < q; ++k) stride[j] *= L; }
+  for (long long r = 0; r < N; ++r) {
+    double h = 0.0;
+    std::vector<int> l(q);
+    for (int j = 0; j < q; ++j) l[j] = (int)((r / stride[j]) % L);
+    for (int j = 0; j < q; ++j) h += D.detuning[j] * l[j] + 0.5 * D.anharmonicity[j] * l[j] * (l[j] - 1);
+    if (D.cross_kerr)
+      for (int j = 0; j + 1 < q; ++j) h += D.cross_kerr[j] * l[j] * l[j + 1];
+    const std::complex<double> di = 1.0 / std::complex<double>(1.0, 0.5 * dt * h);
+    dinv[2 * r] = di.real();
+    dinv[2 * r + 1] = di.imag();
+  }
+  std::vector<int> ess(E);
+  for (int e = 0; e < E; ++e) {
+    long long r = 0;
+    for (int j = 0; j < q; ++j) r += (long long)((e >> (q - 1 - j)) & 1) * stride[j];
+    ess[e] = (int)r;
+  }
+  std::vector<double> Vemb(2 * (size_t)N * E, 0.0);
+  for (int col = 0; col < E; ++col)
+    for (int e = 0; e < E; ++e) {
+      Vemb[2 * ((size_t)col * N + ess[e])] = D.target[2 * (col * E + e)];
+      Vemb[2 * ((size_t)col * N + ess[e]) + 1] = D.target[2 * (col * E + e) + 1];
+    }
+
+  qoc::DevSys &s = c->dev;
+  s.q = q; s.L = L; s.N = (int)N; s.E = E; s.nf = nf; s.d1 = d1; s.M = M; s.NT = NT;
+  s.T = D.T; s.dt = dt; s.dtau = D.T / (double)(d1 - 2); s.mu = D.mu;
+  s.nu_L = ladder_norm(L);
+  s.fp64 = fp64; s.ld = ld; s.cpw = cpw; s.ncg = (E + cpw - 1) / cpw; s.maxlen = maxlen;
+  s.ckpt_every = (D.checkpoint_every > 0 && D.checkpoint_every < maxlen) ? D.checkpoint_every : 0;
+  s.ncp = s.ckpt_every ? (int)((maxlen - 1) / s.ckpt_every) : 0;
+  s.kit_fixed = D.fixed_point_iters;
+  s.solve_tol = D.solve_tol > 0.0 ? D.solve_tol : (fp64 ? std::ldexp(1.0, -54) : std::ldexp(1.0, -26));
+
+  const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
+  const size_t nst = (size_t)M * E * N;           // complex entries of all window states
+  int rc = QOC_OK;
+  long long *kst = nullptr;
+  double *car = nullptr, *dv = nullptr, *Vd = nullptr;
+  int *essd = nullptr;
+#define ALLOC(ptr, bytes_) if (rc == QOC_OK) rc = c->alloc(&(ptr), (bytes_))
+  ALLOC(kst, sizeof(long long) * (M + 1));
+  ALLOC(car, sizeof(double) * q * nf);
+  ALLOC(dv, sizeof(double) * 2 * N);
+  ALLOC(essd, sizeof(int) * E);
+  ALLOC(Vd, sizeof(double) * 2 * N * E);
+  double *alpha = nullptr, *W = nullptr;
+  ALLOC(alpha, sizeof(double) * c->d);
+  ALLOC(W, sizeof(double) * 2 * (size_t)(M - 1) * E * N);
+  ALLOC(s.ctrl, tsz * 2 * (size_t)NT * q);
+  ALLOC(s.Ufin, sizeof(double) * 2 * nst);
+  ALLOC(s.lam0, sizeof(double) * 2 * nst);
+  ALLOC(s.ckpt, sizeof(double) * 2 * nst * s.ncp);
+  ALLOC(s.partials, sizeof(double) * 4 * M);
+  ALLOC(s.scal, sizeof(double) * (5 + M));
+  ALLOC(s.series, sizeof(double) * (size_t)M * s.ncg * maxlen * 2 * q);
+  ALLOC(s.xy, sizeof(double) * (size_t)NT * 2 * q);
+  ALLOC(s.grad_alpha, sizeof(double) * c->d);
+  ALLOC(s.grad_W, sizeof(double) * 2 * (size_t)(M - 1) * E * N);
+  ALLOC(s.kit, sizeof(int) * 2);
+  ALLOC(s.rho_bits, sizeof(unsigned int) * 2);
+  ALLOC(s.status, sizeof(int) * 2);
+#undef ALLOC
+  if (rc != QOC_OK) { delete c; return rc; }
+  s.kstart = kst; s.carrier = car; s.dinv = dv; s.ess_row = essd; s.V = Vd; s.alpha = alpha; s.W = W;
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMemcpy(kst, kstart.data(), sizeof(long long) * (M + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(car, D.carrier_freq, sizeof(double) * q * nf, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dv, dinv.data(), sizeof(double) * 2 * N, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(essd, ess.data(), sizeof(int) * E, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(Vd, Vemb.data(), sizeof(double) * Vemb.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(s.status, 0, sizeof(int) * 2);
+  if (e == hipSuccess) e = hipMemset(s.kit, 0, sizeof(int) * 2);
+  if (e == hipSuccess) e = hipMemset(s.rho_bits, 0, sizeof(unsigned int) * 2);
+  if (e != hipSuccess) { delete c; return hip_fail(e, "qoc_create upload"); }
+  *out = c;
+  return QOC_OK;
+}
+
+int qoc_destroy(qoc_ctx *ctx) {
+  if (!ctx) return QOC_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+  return QOC_OK;
+}
+
+int qoc_get_info(const qoc_ctx *ctx, qoc_info *out) {
+  if (!ctx || !out) return fail(QOC_EINVAL, "qoc_get_info: NULL argument");
+  out->N = ctx->N; out->E = ctx->E; out->d = ctx->d; out->n_windows = ctx->M;
+  out->n_window_doubles = 2LL * (ctx->M - 1) * ctx->N * ctx->E;
+  out->n_terms = 4 + ctx->M;
+  out->lane_digits = ctx->dev.ld;
+  out->columns_per_wave = ctx->dev.cpw;
+  out->device_bytes = (int64_t)ctx->bytes;
+  return QOC_OK;
+}
+
+int qoc_set_stream(qoc_ctx *ctx, void *hip_stream) {
+  if (!ctx) return fail(QOC_EINVAL, "qoc_set_stream: NULL context");
+  ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return QOC_OK;
+}
+
+static hipMemcpyKind kind_in(int32_t where) { return where == QOC_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice; }
+static hipMemcpyKind kind_out(int32_t where) { return where == QOC_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost; }
+
+int qoc_set_controls(qoc_ctx *ctx, const double *alpha, int64_t d, int32_t where) {
+  if (!ctx || !alpha) return fail(QOC_EINVAL, "qoc_set_controls: NULL argument");
+  if (d != ctx->d) return fail(QOC_EINVAL, "qoc_set_controls: expected d = " + std::to_string(ctx->d));
+  if (where != QOC_HOST && where != QOC_DEVICE) return fail(QOC_EINVAL, "qoc_set_controls: bad memory kind");
+  if (where == QOC_HOST && !finite_all(alpha, (size_t)d)) return fail(QOC_EINVAL, "qoc_set_controls: non-finite alpha");
+  HIP_OR_RETURN(hipSetDevice(ctx->device));
+  HIP_OR_RETURN(hipMemcpyAsync(const_cast<double *>(ctx->dev.alpha), alpha, sizeof(double) * d, kind_in(where), ctx->stream));
+  ctx->have_alpha = true;
+  ctx->forward_valid = false;
+  return QOC_OK;
+}
+
+int qoc_set_window_states(qoc_ctx *ctx, const double *W, int64_t n_doubles, int32_t where) {
+  if (!ctx) return fail(QOC_EINVAL, "qoc_set_window_states: NULL context");
+  const int64_t need = 2LL * (ctx->M - 1) * ctx->N * ctx->E;
+  if (n_doubles != need) return fail(QOC_EINVAL, "qoc_set_window_states: expected " + std::to_string(need) + " doubles");
+  if (where != QOC_HOST && where != QOC_DEVICE) return fail(QOC_EINVAL, "qoc_set_window_states: bad memory kind");
+  if (need == 0) { ctx->have_W = true; return QOC_OK; }
+  if (!W) return fail(QOC_EINVAL, "qoc_set_window_states: NULL W");
+  if (where == QOC_HOST && !finite_all(W, (size_t)need)) return fail(QOC_EINVAL, "qoc_set_window_states: non-finite W");
+  HIP_OR_RETURN(hipSetDevice(ctx->device));
+  HIP_OR_RETURN(hipMemcpyAsync(const_cast<double *>(ctx->dev.W), W, sizeof(double) * need, kind_in(where), ctx->stream));
+  ctx->have_W = true;
+  ctx->forward_valid = false;
+  return QOC_OK;
+}
+
+static int check_status(qoc_ctx *ctx) {
+  int st[2] = {0, 0};
+  HIP_OR_RETURN(hipMemcpyAsync(st, ctx->dev.status, sizeof(int) * 2, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_OR_RETURN(hipStreamSynchronize(ctx->stream));
+  if (st[0] & qoc::STATUS_NOTCONV) {
+    HIP_OR_RETURN(hipMemsetAsync(ctx->dev.status, 0, sizeof(int) * 2, ctx->stream));
+    HIP_OR_RETURN(hipStreamSynchronize(ctx->stream));
+    return fail(QOC_ENOTCONV, "fixed-point contraction bound exceeded the solve tolerance (controls too large for dt)");
+  }
+  return QOC_OK;
+}
+
+// Phases [ph0, ph1) of one evaluation (objective: 0..3, gradient: 0..6, backward only: 3..6).
+static int run(qoc_ctx *ctx, int ph0, int ph1, double *P, double *terms, double *ga, double *gW, int32_t where) {
+  const bool grad = ph1 > qoc::PHASE_BOUNDARY + 1;
+  if (!ctx) return fail(QOC_EINVAL, "NULL context");
+  if (where != QOC_HOST && where != QOC_DEVICE) return fail(QOC_EINVAL, "bad memory kind");
+  if (!ctx->have_alpha) return fail(QOC_ESTATE, "controls not set");
+  if (ctx->M > 1 && !ctx->have_W) return fail(QOC_ESTATE, "window states not set");
+  if (ph0 > 0 && !ctx->forward_valid) return fail(QOC_ESTATE, "no objective evaluated for the current inputs");
+  if (grad && !ga) return fail(QOC_EINVAL, "grad_alpha is NULL");
+  HIP_OR_RETURN(hipSetDevice(ctx->device));
+  qoc::DevSys s = ctx->dev;
+  if (grad && where == QOC_DEVICE) {
+    s.grad_alpha = ga;
+    if (gW) s.grad_W = gW;
+  }
+  const bool timed = ctx->timing && ctx->n_timed < qoc_ctx::kTimedCalls;
+  const int call = ctx->n_timed;
+  if (timed) HIP_OR_RETURN(hipEventRecord(ctx->ev(call, ph0), ctx->stream));
+  for (int ph = ph0; ph < ph1; ++ph) {
+    int e = qoc::launch_phase(s, ph, ctx->stream);
+    if (e) { ctx->forward_valid = false; return hip_fail((hipError_t)e, "kernel launch"); }
+    if (timed) HIP_OR_RETURN(hipEventRecord(ctx->ev(call, ph + 1), ctx->stream));
+  }
+  if (ph0 == 0) ctx->forward_valid = true;
+  if (timed) {
+    ctx->call_ph0[call] = (char)ph0;
+    ctx->call_ph1[call] = (char)ph1;
+    ctx->n_timed++;
+  }
+  const hipMemcpyKind k = kind_out(where);
+  if (P) HIP_OR_RETURN(hipMemcpyAsync(P, s.scal, sizeof(double), k, ctx->stream));
+  if (terms) HIP_OR_RETURN(hipMemcpyAsync(terms, s.scal + 1, sizeof(double) * (4 + ctx->M), k, ctx->stream));
+  if (grad && where == QOC_HOST) {
+    HIP_OR_RETURN(hipMemcpyAsync(ga, s.grad_alpha, sizeof(double) * ctx->d, k, ctx->stream));
+    if (gW && ctx->M > 1)
+      HIP_OR_RETURN(hipMemcpyAsync(gW, s.grad_W, sizeof(double) * 2 * (size_t)(ctx->M - 1) * ctx->E * ctx->N, k, ctx->stream));
+  }
+  if (where == QOC_HOST) return check_status(ctx);
+  return QOC_OK;
+}
+
+int qoc_enable_timing(qoc_ctx *ctx, int32_t on) {
+  if (!ctx) return fail(QOC_EINVAL, "qoc_enable_timing: NULL context");
+  HIP_OR_RETURN(hipSetDevice(ctx->device));
+  HIP_OR_RETURN(hipStreamSynchronize(ctx->stream));
+  if (on && ctx->events.empty()) {
+    ctx->events.resize((size_t)qoc_ctx::kTimedCalls * (qoc::N_PHASES + 1));
+    for (auto &e : ctx->events) HIP_OR_RETURN(hipEventCreate(&e));
+    ctx->call_ph0.assign(qoc_ctx::kTimedCalls, 0);
+    ctx->call_ph1.assign(qoc_ctx::kTimedCalls, 0);
+  }
+  ctx->timing = on != 0;
+  ctx->n_timed = 0;
+  return QOC_OK;
+}
+
+int qoc_get_timings(qoc_ctx *ctx, qoc_timings *out) {
+  if (!ctx || !out) return fail(QOC_EINVAL, "qoc_get_timings: NULL argument");
+  HIP_OR_RETURN(hipSetDevice(ctx->device));
+  HIP_OR_RETURN(hipStreamSynchronize(ctx->stream));
+  std::memset(out, 0, sizeof *out);
+  double sum[8] = {0};
+  int cnt[8] = {0};
+  int ngrad = 0;
+  for (int c = 0; c < ctx->n_timed; ++c) {
+    const int p0 = ctx->call_ph0[c], p1 = ctx->call_ph1[c];
+    ngrad += p1 > qoc::PHASE_BOUNDARY + 1 ? 1 : 0;
+    for (int ph = p0; ph < p1; ++ph) {
+      float ms = 0.f;
+      HIP_OR_RETURN(hipEventElapsedTime(&ms, ctx->ev(c, ph), ctx->ev(c, ph + 1)));
+      sum[ph] += ms;
+      cnt[ph]++;
+    }
+    float tot = 0.f;
+    HIP_OR_RETURN(hipEventElapsedTime(&tot, ctx->ev(c, p0), ctx->ev(c, p1)));
+    sum[6] += tot;
+    cnt[6]++;
+  }
+  out->n_calls = ctx->n_timed;
+  out->n_grad_calls = ngrad;
+  for (int ph = 0; ph < 7; ++ph) out->mean_ms[ph] = cnt[ph] ? sum[ph] / cnt[ph] : 0.0;
+  int kit = 0;
+  if (ctx->dev.kit_fixed > 0) kit = ctx->dev.kit_fixed;
+  else HIP_OR_RETURN(hipMemcpy(&kit, ctx->dev.kit, sizeof(int), hipMemcpyDeviceToHost));
+  out->fixed_point_iters = kit;
+  return QOC_OK;
+}
+
+int qoc_objective(qoc_ctx *ctx, double *P, double *terms, int32_t where) {
+  if (!P) return fail(QOC_EINVAL, "qoc_objective: NULL P");
+  return run(ctx, 0, qoc::PHASE_BOUNDARY + 1, P, terms, nullptr, nullptr, where);
+}
+
+int qoc_gradient(qoc_ctx *ctx, double *P, double *terms, double *grad_alpha, double *grad_W, int32_t where) {
+  return run(ctx, 0, qoc::PHASE_GRAD_W + 1, P, terms, grad_alpha, grad_W, where);
+}
+
+int qoc_backward(qoc_ctx *ctx, double *grad_alpha, double *grad_W, int32_t where) {
+  return run(ctx, qoc::PHASE_BACKWARD, qoc::PHASE_GRAD_W + 1, nullptr, nullptr, grad_alpha, grad_W, where);
+}
+
+int qoc_rollout(qoc_ctx *ctx, double *W_out, double *U_out, int32_t where) {
+  if (!ctx) return fail(QOC_EINVAL, "qoc_rollout: NULL context");
+  if (where != QOC_HOST && where != QOC_DEVICE) return fail(QOC_EINVAL, "qoc_rollout: bad memory kind");
+  if (!ctx->have_alpha) return fail(QOC_ESTATE, "controls not set");
+  HIP_OR_RETURN(hipSetDevice(ctx->device));
+  const size_t nW = 2 * (size_t)(ctx->M - 1) * ctx->E * ctx->N, nU = 2 * (size_t)ctx->E * ctx->N;
+  double *wd = W_out, *ud = U_out;
+  if (where == QOC_HOST) {
+    if (!ctx->roll_W) {
+      int rc = ctx->alloc(&ctx->roll_W, sizeof(double) * std::max<size_t>(nW, 2));
+      if (rc == QOC_OK) rc = ctx->alloc(&ctx->roll_U, sizeof(double) * nU);
+      if (rc != QOC_OK) return rc;
+    }
+    wd = ctx->roll_W;
+    ud = ctx->roll_U;
+  }
+  if (!wd) {
+    if (!ctx->roll_W) {
+      int rc = ctx->alloc(&ctx->roll_W, sizeof(double) * std::max<size_t>(nW, 2));
+      if (rc == QOC_OK) rc = ctx->alloc(&ctx->roll_U, sizeof(double) * nU);
+      if (rc != QOC_OK) return rc;
+    }
+    wd = ctx->roll_W;
+  }
+  int e = qoc::launch_phase(ctx->dev, qoc::PHASE_CONTROLS, ctx->stream);
+  if (!e) e = qoc::launch_phase(ctx->dev, qoc::PHASE_ROLLOUT, ctx->stream, wd, ud);
+  if (e) return hip_fail((hipError_t)e, "roll-out kernels");
+  if (where == QOC_HOST) {
+    if (W_out && nW) HIP_OR_RETURN(hipMemcpyAsync(W_out, wd, sizeof(double) * nW, hipMemcpyDeviceToHost, ctx->stream));
+    if (U_out) HIP_OR_RETURN(hipMemcpyAsync(U_out, ud, sizeof(double) * nU, hipMemcpyDeviceToHost, ctx->stream));
+    return check_status(ctx);
+  }
+  return QOC_OK;
+}
+
+int qoc_synchronize(qoc_ctx *ctx) {
+  if (!ctx) return fail(QOC_EINVAL, "qoc_synchronize: NULL context");
+  HIP_OR_RETURN(hipSetDevice(ctx->device));
+  return check_status(ctx);
+}
+
+}  // extern "C"

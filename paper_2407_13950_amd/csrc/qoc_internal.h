@@ -1,0 +1,67 @@
+// Internal interface between the C-ABI host code (qoc_api.cpp) and the HIP
+// kernels (qoc_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace qoc {
+
+// Everything one evaluation needs on the device, as plain pointers and sizes.
+// Complex arrays are interleaved (re, im).  The control table holds the
+// propagation precision (float for the FP32 path, double for the FP64 path);
+// states, adjoints, reductions and gradients are double in both paths.
+struct DevSys {
+  int q, L, N, E, nf, d1, M;
+  long long NT;
+  double T, dt, dtau, mu;
+  double nu_L;              // ||a + a^+||_2 for L levels (fixed-point contraction bound)
+  int fp64;                 // 1: propagation in double, 0: float
+  int ld;                   // lane digits of the register layout
+  int cpw;                  // state columns per wavefront
+  int ncg;                  // column groups (wavefronts) per window
+  long long maxlen;         // longest window, steps
+  int ckpt_every;           // checkpoint spacing in steps (0 = none)
+  int ncp;                  // checkpoints stored per window
+  int kit_fixed;            // > 0: fixed-point iterations forced by the caller
+  double solve_tol;         // per-step truncation target of the fixed point
+
+  const long long *kstart;  // [M+1] first step of each window (floor split)
+  const double *carrier;    // [q*nf] rad/ns
+  const double *dinv;       // [2N] complex: 1/(1 + i dt/2 h_r)
+  const int *ess_row;       // [E]
+  const double *V;          // [2*N*E] target embedded in the essential rows, column-major
+  const double *alpha;      // [d]
+  const double *W;          // [2*(M-1)*E*N]: W^1..W^{M-1}, column-major N x E each
+
+  void *ctrl;               // [NT*q] complex T: (dt/2) * 2 pi d_j(t_{k+1/2})
+  double *Ufin;             // [2*M*E*N] complex: U^m(t_m)
+  double *lam0;             // [2*M*E*N] complex: propagated adjoint at t_{m-1}
+  double *ckpt;             // [2*M*ncp*E*N] complex checkpoints
+  double *partials;         // [4*M]
+  double *scal;             // [5+M]: P, J, penalty, |U^M|^2, Re gamma, Im gamma, |C^1|^2..|C^{M-1}|^2
+  double *series;           // [M*ncg*maxlen*2q]: per wavefront and step, Im<y,(a+a^+)z>, Re<y,(a-a^+)z>
+  double *xy;               // [NT*2q]: the same summed over the window's columns
+  double *grad_alpha;       // [d]
+  double *grad_W;           // [2*(M-1)*E*N]
+  int *kit;                 // [1] fixed-point iterations in use
+  unsigned int *rho_bits;   // [1] max per-step contraction bound (float bits), reset by k_kit
+  int *status;              // [1] device-side status bits (QOC_STATUS_*)
+};
+
+enum { STATUS_NOTCONV = 1 };
+
+// Layout chosen for a (q, L) pair: lane digits and columns per wavefront.
+// Returns false when no kernel instance exists for the pair.
+bool layout_for(int q, int L, int fp64, int *ld, int *cpw);
+
+// Phases of one evaluation, launched in this order on one stream:
+// objective = CONTROLS, FORWARD, BOUNDARY; gradient adds BACKWARD, PROJECT, GRAD_W.
+// ROLLOUT (after CONTROLS) is the single-window propagation over [0, T].
+enum Phase { PHASE_CONTROLS = 0, PHASE_FORWARD, PHASE_BOUNDARY, PHASE_BACKWARD, PHASE_PROJECT, PHASE_GRAD_W,
+             PHASE_ROLLOUT, N_PHASES };
+
+// Returns 0 or a hipError_t value.
+int launch_phase(const DevSys &s, int phase, hipStream_t st, double *Wout = nullptr, double *Ufinal = nullptr);
+
+}  // namespace qoc

@@ -1,0 +1,790 @@
+// CDNA4 (gfx950) kernels for the multiple-shooting penalty objective and its
+// discrete-adjoint gradient (arxiv 2407.13950).
+//
+// Data path of one objective+gradient evaluation:
+//   k_kit            fixed-point iteration count from a 2-norm contraction bound
+//   k_controls       per time step: (dt/2) * 2 pi d_j(t_{k+1/2})                        (Sec. 2, eq. dj-ctrl)
+//   k_forward        per (window, column group): implicit-midpoint propagation from W^{m-1}
+//                    with the state held in registers for the whole window               (Sec. 3, eqs. sch-op/sch-ic; Sec. 5)
+//   k_boundary_*     FP64 penalty |U^m - W^m|^2, |U^M|^2, gamma = <V, U^M>, P            (eqs. mod-infid, penalty-fcn)
+//   k_backward       per (window, column group): terminal condition (eq. terminal), reverse
+//                    reconstruction of U and the discrete adjoint in one fused sweep, per-step
+//                    inner products for the control gradient                            (eq. grad-int, discrete form)
+//   k_series_reduce  sum of the per-step inner products over a window's column groups
+//   k_project        B-spline x carrier projection onto dP/dalpha (FP64)
+//   k_grad_W         dP/dW^m = mu (W^m - U^m) - 2 Lambda^{m+1}(t_m)                      (App. B, eq. dT-dW-j)
+//
+// Register layout of the propagation kernels.  A state column of N = L^q
+// entries is spread over LPC = L^LD lanes of one wavefront; each lane holds
+// EPL = L^(q-LD) entries in registers.  Row r = e*LPC + sub, where e is the
+// register slot and sub the lane's position in its column.  The q digits of r
+// (qubit 0 most significant) split into "register digits" (the leading q-LD,
+// encoded in e) and "lane digits" (the trailing LD, encoded in sub).  A ladder
+// operator on a register digit reads another register of the same lane (no data
+// movement); on a lane digit it reads the same register of the lane +-L^k away
+// (cross-lane permute).  A wavefront holds CPW = 64/pow2ceil(LPC) columns of one
+// window, so all its lanes see the same control values at every step.
+//
+// One fixed-point (Jacobi) iteration for (I + i dt/2 H) z = u with the diagonal
+// drift D = I + i dt/2 diag(h) split off:  z <- D^{-1} (u - i S), S = (dt/2) H_c z.
+#include "qoc_internal.h"
+
+#include <cmath>
+#include <cstdio>
+
+namespace qoc {
+namespace {
+
+constexpr int cipow(int b, int e) { return e <= 0 ? 1 : b * cipow(b, e - 1); }
+constexpr int cpow2(int x) { return x <= 1 ? 1 : 2 * cpow2((x + 1) / 2); }
+
+template <typename T> struct C2 { using type = float2; };
+template <> struct C2<double> { using type = double2; };
+
+template <typename T, int Q, int L, int LD>
+struct Geo {
+  static constexpr int N = cipow(L, Q);
+  static constexpr int R = Q - LD;               // register digits
+  static constexpr int EPL = cipow(L, R);        // entries per lane
+  static constexpr int LPC = cipow(L, LD);       // lanes per column
+  static constexpr int LPCP = cpow2(LPC);        // padded to a power of two
+  static constexpr int CPW = 64 / LPCP;          // columns per wavefront
+  static_assert(LPCP <= 64, "a column must fit in one wavefront");
+  static constexpr int rstride(int j) { return cipow(L, R - 1 - j); }   // register digit j < R
+  static constexpr int rdigit(int e, int j) { return (e / rstride(j)) % L; }
+  static constexpr int lstride(int jj) { return cipow(L, LD - 1 - jj); } // lane digit jj (qubit R+jj)
+};
+
+// Blocks are dealt to the 8 XCDs round-robin; map consecutive work items
+// (column groups of one window, which read the same control-table slice) to
+// one XCD's L2.  The grid is padded to a multiple of 8; items past the end exit.
+__device__ __forceinline__ int xcd_item(int b, int nblk) {
+  const int per = nblk / 8;
+  return (b % 8) * per + b / 8;
+}
+
+__device__ __forceinline__ double bspline2(double x) {
+  const double a = fabs(x);
+  if (a < 0.5) return 0.75 - a * a;
+  if (a < 1.5) return 0.5 * (a - 1.5) * (a - 1.5);
+  return 0.0;
+}
+
+// ---------------------------------------------------------------------------- per-lane state
+
+// Lane shift for lane digit jj: DPP row shift when every shifted pair stays in
+// one 16-lane row (L a power of two and the digit block L^(k+1) <= 16), else a
+// cross-lane permute through the LDS crossbar.
+template <int L, int ST>
+struct ShiftKind {
+  static constexpr bool pow2 = (L & (L - 1)) == 0;
+  static constexpr bool dpp = pow2 && ST * L <= 16;
+};
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// value of lane (lane + ST) (UP) or (lane - ST) (down); meaningful only where the
+// ladder coefficient is nonzero, i.e. where that lane holds the neighbouring row.
+template <typename T, int L, int ST, bool UP>
+__device__ __forceinline__ T lane_shift(T v, int src) {
+  if constexpr (ShiftKind<L, ST>::dpp) {
+    constexpr int ctrl = UP ? (0x100 + ST) : (0x110 + ST);   // row_shl:ST reads lane+ST, row_shr:ST reads lane-ST
+    if constexpr (sizeof(T) == 4) return dpp_f32<ctrl>(v);
+    else return dpp_f64<ctrl>(v);
+  } else {
+    return __shfl(v, src, 64);
+  }
+}
+
+template <typename T, int Q, int L, int LD>
+struct Lane {
+  using G = Geo<T, Q, L, LD>;
+  int lane, sub, col;
+  bool valid;
+  int up[LD > 0 ? LD : 1], dn[LD > 0 ? LD : 1];     // permute sources for lane digits
+  T wlo[LD > 0 ? LD : 1], whi[LD > 0 ? LD : 1];     // sqrt(l+1) (0 at the top level), sqrt(l) (0 at l = 0)
+  T dr[G::EPL], di[G::EPL];                         // D^{-1} per entry
+  // D^{-1} - 1 split into a rounded part and its remainder.  The same factor
+  // multiplies every step, so in FP32 its rounding error would accumulate
+  // linearly over a window; the remainder removes that drift.
+  T mr[G::EPL], mi[G::EPL], mrl[G::EPL], mil[G::EPL];
+
+  __device__ void init(const DevSys &s, int cg) {
+    lane = threadIdx.x;
+    const int slot = lane / G::LPCP;
+    sub = lane % G::LPCP;
+    col = cg * G::CPW + slot;
+    valid = (sub < G::LPC) && (col < s.E);
+#pragma unroll
+    for (int jj = 0; jj < LD; ++jj) {
+      const int st = G::lstride(jj);
+      const int l = valid ? (sub / st) % L : 0;
+      up[jj] = (valid && l < L - 1) ? lane + st : lane;
+      dn[jj] = (valid && l > 0) ? lane - st : lane;
+      wlo[jj] = (valid && l < L - 1) ? (T)sqrt((double)(l + 1)) : (T)0;
+      whi[jj] = (valid && l > 0) ? (T)sqrt((double)l) : (T)0;
+    }
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {
+      const int r = e * G::LPC + sub;
+      const double a = valid ? s.dinv[2 * r] : 1.0, b = valid ? s.dinv[2 * r + 1] : 0.0;
+      dr[e] = (T)a;
+      di[e] = (T)b;
+      mr[e] = (T)(a - 1.0);
+      mi[e] = (T)b;
+      mrl[e] = (T)((a - 1.0) - (double)mr[e]);
+      mil[e] = (T)(b - (double)mi[e]);
+    }
+  }
+  __device__ __forceinline__ int row(int e) const { return e * G::LPC + sub; }
+  // x = (D^{-1} - 1) u  (CONJ: (conj(D)^{-1} - 1) u), remainder first.
+  template <bool CONJ>
+  __device__ __forceinline__ void scale_m1(int e, T ur, T ui, T &xr, T &xi) const {
+    const T sg = CONJ ? (T)-1 : (T)1;
+    if constexpr (sizeof(T) == 4) {
+      xr = (mrl[e] * ur - sg * mil[e] * ui) + mr[e] * ur - sg * mi[e] * ui;
+      xi = (mrl[e] * ui + sg * mil[e] * ur) + mr[e] * ui + sg * mi[e] * ur;
+    } else {
+      xr = mr[e] * ur - sg * mi[e] * ui;
+      xi = mr[e] * ui + sg * mi[e] * ur;
+    }
+  }
+};
+
+// S = (dt/2) H_c v for this lane's entries.  cr/ci: per-qubit scaled control
+// c'_j = (dt/2) 2 pi d_j; the coefficient of a_j is c'_j, of a_j^+ conj(c'_j).
+template <typename T, int Q, int L, int LD, int JJ = 0>
+__device__ __forceinline__ void apply_lane_digits(const Lane<T, Q, L, LD> &ln, const T *lor, const T *loi,
+                                                  const T *hir, const T *hii, const T *vr, const T *vi, T *Sr, T *Si) {
+  using G = Geo<T, Q, L, LD>;
+  if constexpr (JJ < LD) {
+    constexpr int ST = G::lstride(JJ);
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {
+      const T ur = lane_shift<T, L, ST, true>(vr[e], ln.up[JJ]), ui = lane_shift<T, L, ST, true>(vi[e], ln.up[JJ]);
+      const T dr_ = lane_shift<T, L, ST, false>(vr[e], ln.dn[JJ]), di_ = lane_shift<T, L, ST, false>(vi[e], ln.dn[JJ]);
+      Sr[e] += lor[JJ] * ur - loi[JJ] * ui + hir[JJ] * dr_ - hii[JJ] * di_;
+      Si[e] += lor[JJ] * ui + loi[JJ] * ur + hir[JJ] * di_ + hii[JJ] * dr_;
+    }
+    apply_lane_digits<T, Q, L, LD, JJ + 1>(ln, lor, loi, hir, hii, vr, vi, Sr, Si);
+  }
+}
+
+template <typename T, int Q, int L, int LD>
+__device__ __forceinline__ void apply_Hc(const Lane<T, Q, L, LD> &ln, const T *cr, const T *ci,
+                                         const T *lor, const T *loi, const T *hir, const T *hii,
+                                         const T *vr, const T *vi, T *Sr, T *Si) {
+  using G = Geo<T, Q, L, LD>;
+#pragma unroll
+  for (int e = 0; e < G::EPL; ++e) { Sr[e] = 0; Si[e] = 0; }
+#pragma unroll
+  for (int j = 0; j < G::R; ++j) {
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {
+      const int l = G::rdigit(e, j);
+      const int st = G::rstride(j);
+      if (l < L - 1) {  // c'_j sqrt(l+1) v[e+st]
+        const T ar = cr[j] * (T)sqrt((double)(l + 1)), ai = ci[j] * (T)sqrt((double)(l + 1));
+        Sr[e] += ar * vr[e + st] - ai * vi[e + st];
+        Si[e] += ar * vi[e + st] + ai * vr[e + st];
+      }
+      if (l > 0) {      // conj(c'_j) sqrt(l) v[e-st]
+        const T ar = cr[j] * (T)sqrt((double)l), ai = ci[j] * (T)sqrt((double)l);
+        Sr[e] += ar * vr[e - st] + ai * vi[e - st];
+        Si[e] += ar * vi[e - st] - ai * vr[e - st];
+      }
+    }
+  }
+  apply_lane_digits<T, Q, L, LD>(ln, lor, loi, hir, hii, vr, vi, Sr, Si);
+}
+
+// Per-step control coefficients: c'_j for register digits, per-lane lowering
+// (c'_j sqrt(l+1)) and raising (conj(c'_j) sqrt(l)) coefficients for lane digits.
+template <typename T, int Q, int L, int LD>
+__device__ __forceinline__ void step_coeffs(const Lane<T, Q, L, LD> &ln, const T *ctrl, long long k, T *cr, T *ci,
+                                            T *lor, T *loi, T *hir, T *hii) {
+  using V2 = typename C2<T>::type;
+  const V2 *c = reinterpret_cast<const V2 *>(ctrl) + k * Q;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const V2 v = c[j];
+    cr[j] = v.x;
+    ci[j] = v.y;
+  }
+#pragma unroll
+  for (int jj = 0; jj < LD; ++jj) {
+    const int j = Geo<T, Q, L, LD>::R + jj;
+    lor[jj] = cr[j] * ln.wlo[jj];
+    loi[jj] = ci[j] * ln.wlo[jj];
+    hir[jj] = cr[j] * ln.whi[jj];
+    hii[jj] = -ci[j] * ln.whi[jj];
+  }
+}
+
+__device__ __forceinline__ int kit_of(const DevSys &s) { return s.kit_fixed > 0 ? s.kit_fixed : *s.kit; }
+
+// One implicit-midpoint solve for the increment w = z - u, with z the solution of
+// (I + sg i dt/2 H) z = u (sg = +1 forward, -1 reverse/adjoint).  With
+// D = I + sg i dt/2 diag(h):  w = (D^{-1} - 1) u - sg i D^{-1} (dt/2) H_c (u + w),
+// iterated kit times from w = (D^{-1} - 1) u (the Jacobi splitting of the solve).
+// The increment is O(dt |H|) |u| small, so its FP32 rounding enters the FP64
+// state only at that scale.
+template <typename T, int Q, int L, int LD, bool REV>
+__device__ __forceinline__ void solve_increment(const Lane<T, Q, L, LD> &ln, int kit, const T *cr, const T *ci,
+                                                const T *lor, const T *loi, const T *hir, const T *hii,
+                                                const T *ur, const T *ui, T *wr, T *wi) {
+  using G = Geo<T, Q, L, LD>;
+  T xr[G::EPL], xi[G::EPL], vr[G::EPL], vi[G::EPL], Sr[G::EPL], Si[G::EPL];
+#pragma unroll
+  for (int e = 0; e < G::EPL; ++e) {
+    ln.template scale_m1<REV>(e, ur[e], ui[e], xr[e], xi[e]);
+    wr[e] = xr[e];
+    wi[e] = xi[e];
+  }
+  for (int it = 0; it < kit; ++it) {
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {
+      vr[e] = ur[e] + wr[e];
+      vi[e] = ui[e] + wi[e];
+    }
+    apply_Hc<T, Q, L, LD>(ln, cr, ci, lor, loi, hir, hii, vr, vi, Sr, Si);
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {
+      if (!REV) {   // w = x - i D^{-1} S
+        wr[e] = xr[e] + ln.dr[e] * Si[e] + ln.di[e] * Sr[e];
+        wi[e] = xi[e] - ln.dr[e] * Sr[e] + ln.di[e] * Si[e];
+      } else {      // w = x + i conj(D)^{-1} S
+        wr[e] = xr[e] - ln.dr[e] * Si[e] + ln.di[e] * Sr[e];
+        wi[e] = xi[e] + ln.dr[e] * Sr[e] + ln.di[e] * Si[e];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------- forward sweep
+
+// One wavefront per (window, column group).  The state U (FP64 accumulator)
+// starts from W^{m-1} (W^0 = I), advances over the window's steps entirely in
+// registers, u_{k+1} = u_k + 2 w_k, and is written as U^m(t_m); optional
+// checkpoints U_{k0 + i*C} are written on the way.  ROLLOUT: a single window over
+// all steps from W^0, writing the states at the window boundaries instead.
+template <typename T, int Q, int L, int LD, bool ROLLOUT>
+__global__ __launch_bounds__(64) void k_forward(DevSys s, double *Wout, double *Uout, int nitems) {
+  using G = Geo<T, Q, L, LD>;
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  if (item >= nitems) return;
+  const int m = ROLLOUT ? 0 : item / s.ncg;      // 0-based window
+  const int cg = ROLLOUT ? item : item % s.ncg;
+  Lane<T, Q, L, LD> ln;
+  ln.init(s, cg);
+
+  double udr[G::EPL], udi[G::EPL];
+#pragma unroll
+  for (int e = 0; e < G::EPL; ++e) {
+    udr[e] = 0.0;
+    udi[e] = 0.0;
+    if (ln.valid) {
+      const int r = ln.row(e);
+      if (m == 0) {
+        udr[e] = (r == s.ess_row[ln.col]) ? 1.0 : 0.0;
+      } else {
+        const double2 w = reinterpret_cast<const double2 *>(s.W)[((size_t)(m - 1) * s.E + ln.col) * s.N + r];
+        udr[e] = w.x;
+        udi[e] = w.y;
+      }
+    }
+  }
+  const long long k0 = ROLLOUT ? 0 : s.kstart[m];
+  const long long k1 = ROLLOUT ? s.NT : s.kstart[m + 1];
+  const int kit = kit_of(s);
+  const T *ctrl = reinterpret_cast<const T *>(s.ctrl);
+  int next_boundary = 1;
+
+  for (long long k = k0; k < k1; ++k) {
+    if (!ROLLOUT && s.ckpt_every > 0 && k > k0 && (k - k0) % s.ckpt_every == 0) {
+      const long long i = (k - k0) / s.ckpt_every - 1;
+      double2 *cp = reinterpret_cast<double2 *>(s.ckpt) + (((size_t)m * s.ncp + i) * s.E + ln.col) * s.N;
+      if (ln.valid)
+#pragma unroll
+        for (int e = 0; e < G::EPL; ++e) cp[ln.row(e)] = double2{udr[e], udi[e]};
+    }
+    T cr[Q], ci[Q], lor[LD > 0 ? LD : 1], loi[LD > 0 ? LD : 1], hir[LD > 0 ? LD : 1], hii[LD > 0 ? LD : 1];
+    step_coeffs<T, Q, L, LD>(ln, ctrl, k, cr, ci, lor, loi, hir, hii);
+    T ur[G::EPL], ui[G::EPL], wr[G::EPL], wi[G::EPL];
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {
+      ur[e] = (T)udr[e];
+      ui[e] = (T)udi[e];
+    }
+    solve_increment<T, Q, L, LD, false>(ln, kit, cr, ci, lor, loi, hir, hii, ur, ui, wr, wi);
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {   // u_{k+1} = 2 z - u_k = u_k + 2 w
+      udr[e] += 2.0 * (double)wr[e];
+      udi[e] += 2.0 * (double)wi[e];
+    }
+    if (ROLLOUT && next_boundary < s.M && k + 1 == s.kstart[next_boundary]) {
+      if (ln.valid) {
+        double2 *w = reinterpret_cast<double2 *>(Wout) + ((size_t)(next_boundary - 1) * s.E + ln.col) * s.N;
+#pragma unroll
+        for (int e = 0; e < G::EPL; ++e) w[ln.row(e)] = double2{udr[e], udi[e]};
+      }
+      ++next_boundary;
+    }
+  }
+  if (!ln.valid) return;
+  double2 *dst = ROLLOUT ? reinterpret_cast<double2 *>(Uout) + (size_t)ln.col * s.N
+                         : reinterpret_cast<double2 *>(s.Ufin) + ((size_t)m * s.E + ln.col) * s.N;
+  if (ROLLOUT && !Uout) return;
+#pragma unroll
+  for (int e = 0; e < G::EPL; ++e) dst[ln.row(e)] = double2{udr[e], udi[e]};
+}
+
+// Lane-digit part of the per-step inner products.
+template <typename T, int Q, int L, int LD, int JJ = 0>
+__device__ __forceinline__ void inner_lane_digits(const Lane<T, Q, L, LD> &ln, const T *zr, const T *zi, const T *yr,
+                                                  const T *yi, T *s1, T *s2) {
+  using G = Geo<T, Q, L, LD>;
+  if constexpr (JJ < LD) {
+    constexpr int ST = G::lstride(JJ);
+    T a1 = 0, a2 = 0;
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {
+      const T zur = lane_shift<T, L, ST, true>(zr[e], ln.up[JJ]), zui = lane_shift<T, L, ST, true>(zi[e], ln.up[JJ]);
+      const T yur = lane_shift<T, L, ST, true>(yr[e], ln.up[JJ]), yui = lane_shift<T, L, ST, true>(yi[e], ln.up[JJ]);
+      a1 += yr[e] * zui - yi[e] * zur + yur * zi[e] - yui * zr[e];
+      a2 += yr[e] * zur + yi[e] * zui - yur * zr[e] - yui * zi[e];
+    }
+    s1[G::R + JJ] = ln.wlo[JJ] * a1;
+    s2[G::R + JJ] = ln.wlo[JJ] * a2;
+    inner_lane_digits<T, Q, L, LD, JJ + 1>(ln, zr, zi, yr, yi, s1, s2);
+  }
+}
+
+// ---------------------------------------------------------------------------- backward sweep
+
+// FP64 sum over the wavefront; every lane receives the total.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// One wavefront per (window, column group).  Starting from U^m(t_m) and the
+// terminal condition of eq. terminal, each step k (descending) solves
+//   (I - i dt/2 H_k) [z, y] = [U_{k+1}, Lambda_{k+1}]
+// with one shared fixed point: z = (U_k + U_{k+1})/2 reconstructs the forward
+// state (the rule is time-reversible), y is the adjoint midpoint.  Then
+//   U_k = 2z - U_{k+1},  Lambda_k = 2y - Lambda_{k+1},
+// and the per-step inner products Im<y, (a_j + a_j^+) z>, Re<y, (a_j - a_j^+) z>
+// (summed over the wavefront's columns, in FP64 across lanes) go to the series.
+//
+// Last window: Lambda^M(t_M) = gamma V/E^2 - U^M/E.  The part -U^M/E obeys the
+// same backward recursion as U itself, so at every step it equals -z/E and adds
+// Re<z, i dH z>/E = 0 to the control gradient (dH Hermitian); only gamma V/E^2 is
+// propagated, and the W-gradient adds the dropped part back exactly:
+// Lambda^M(t_{M-1}) = -W^{M-1}/E + (propagated part)  (App. B, eq. back-prop-2).
+template <typename T, int Q, int L, int LD>
+__global__ __launch_bounds__(64) void k_backward(DevSys s, int nitems) {
+  using G = Geo<T, Q, L, LD>;
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  if (item >= nitems) return;
+  const int m = item / s.ncg;
+  const int cg = item % s.ncg;
+  Lane<T, Q, L, LD> ln;
+  ln.init(s, cg);
+
+  double udr[G::EPL], udi[G::EPL], ldr[G::EPL], ldi[G::EPL];
+  {
+    const double2 *uf = reinterpret_cast<const double2 *>(s.Ufin) + ((size_t)m * s.E + ln.col) * s.N;
+    const double E2 = (double)s.E * (double)s.E;
+    const double gr = s.scal[4] / E2, gi = s.scal[5] / E2;
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {
+      udr[e] = udi[e] = ldr[e] = ldi[e] = 0.0;
+      if (!ln.valid) continue;
+      const int r = ln.row(e);
+      const double2 u = uf[r];
+      udr[e] = u.x;
+      udi[e] = u.y;
+      if (m < s.M - 1) {          // mu/2 (W^m - U^m)
+        const double2 w = reinterpret_cast<const double2 *>(s.W)[((size_t)m * s.E + ln.col) * s.N + r];
+        ldr[e] = 0.5 * s.mu * (w.x - u.x);
+        ldi[e] = 0.5 * s.mu * (w.y - u.y);
+      } else {                    // gamma V / E^2
+        const double2 v = reinterpret_cast<const double2 *>(s.V)[(size_t)ln.col * s.N + r];
+        ldr[e] = gr * v.x - gi * v.y;
+        ldi[e] = gr * v.y + gi * v.x;
+      }
+    }
+  }
+  const long long k0 = s.kstart[m], k1 = s.kstart[m + 1];
+  const int kit = kit_of(s);
+  const T *ctrl = reinterpret_cast<const T *>(s.ctrl);
+  double *ser = s.series + (size_t)item * s.maxlen * 2 * Q;
+
+  for (long long k = k1 - 1; k >= k0; --k) {
+    T cr[Q], ci[Q], lor[LD > 0 ? LD : 1], loi[LD > 0 ? LD : 1], hir[LD > 0 ? LD : 1], hii[LD > 0 ? LD : 1];
+    step_coeffs<T, Q, L, LD>(ln, ctrl, k, cr, ci, lor, loi, hir, hii);
+    T ur[G::EPL], ui[G::EPL], lr[G::EPL], li[G::EPL];
+    T wur[G::EPL], wui[G::EPL], wlr[G::EPL], wli[G::EPL];
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {
+      ur[e] = (T)udr[e];
+      ui[e] = (T)udi[e];
+      lr[e] = (T)ldr[e];
+      li[e] = (T)ldi[e];
+    }
+    solve_increment<T, Q, L, LD, true>(ln, kit, cr, ci, lor, loi, hir, hii, ur, ui, wur, wui);
+    solve_increment<T, Q, L, LD, true>(ln, kit, cr, ci, lor, loi, hir, hii, lr, li, wlr, wli);
+    T zr[G::EPL], zi[G::EPL], yr[G::EPL], yi[G::EPL];
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {
+      zr[e] = ur[e] + wur[e];
+      zi[e] = ui[e] + wui[e];
+      yr[e] = lr[e] + wlr[e];
+      yi[e] = li[e] + wli[e];
+    }
+    // inner products per qubit: s1 = Im(A + B), s2 = Re(A - B) with
+    // A = <y, a_j z> = sum conj(y_r) sqrt(l+1) z_{r+st},  B = <y, a_j^+ z> = sum sqrt(l+1) conj(y_{r+st}) z_r
+    T s1[Q], s2[Q];
+#pragma unroll
+    for (int j = 0; j < G::R; ++j) {
+      s1[j] = 0;
+      s2[j] = 0;
+#pragma unroll
+      for (int e = 0; e < G::EPL; ++e) {
+        const int l = G::rdigit(e, j);
+        if (l < L - 1) {
+          const int f = e + G::rstride(j);
+          const T w = (T)sqrt((double)(l + 1));
+          s1[j] += w * (yr[e] * zi[f] - yi[e] * zr[f] + yr[f] * zi[e] - yi[f] * zr[e]);
+          s2[j] += w * (yr[e] * zr[f] + yi[e] * zi[f] - yr[f] * zr[e] - yi[f] * zi[e]);
+        }
+      }
+    }
+    inner_lane_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
+    double v[2 * Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      v[2 * j] = wave_sum((double)s1[j]);
+      v[2 * j + 1] = wave_sum((double)s2[j]);
+    }
+    if (ln.lane == 0) {
+      double *dst = ser + (size_t)(k - k0) * 2 * Q;
+#pragma unroll
+      for (int i = 0; i < 2 * Q; ++i) dst[i] = v[i];
+    }
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {
+      udr[e] += 2.0 * (double)wur[e];
+      udi[e] += 2.0 * (double)wui[e];
+      ldr[e] += 2.0 * (double)wlr[e];
+      ldi[e] += 2.0 * (double)wli[e];
+    }
+    if (s.ckpt_every > 0 && k > k0 && (k - k0) % s.ckpt_every == 0) {   // re-sync to the stored state
+      const long long i = (k - k0) / s.ckpt_every - 1;
+      const double2 *cp = reinterpret_cast<const double2 *>(s.ckpt) + (((size_t)m * s.ncp + i) * s.E + ln.col) * s.N;
+      if (ln.valid)
+#pragma unroll
+        for (int e = 0; e < G::EPL; ++e) {
+          const double2 c = cp[ln.row(e)];
+          udr[e] = c.x;
+          udi[e] = c.y;
+        }
+    }
+  }
+  if (!ln.valid) return;
+  double2 *l0 = reinterpret_cast<double2 *>(s.lam0) + ((size_t)m * s.E + ln.col) * s.N;
+#pragma unroll
+  for (int e = 0; e < G::EPL; ++e) l0[ln.row(e)] = double2{ldr[e], ldi[e]};
+}
+
+// ---------------------------------------------------------------------------- small FP64 kernels
+
+// Fixed-point iteration count.  The Jacobi map w -> (D^{-1} - 1)u - i D^{-1} (dt/2) H_c (u + w)
+// contracts in the 2-norm by rho_k <= |D^{-1}| nu_L sum_j |c'_j(t_k)| with |D^{-1}| <= 1,
+// c'_j = (dt/2) 2 pi d_j and nu_L = ||a + a^+||_2; k_controls leaves max_k of that bound
+// in rho_bits.  Starting from w = (D^{-1} - 1)u, K iterations leave an error
+// <= rho^(K+1) |z|; K is the smallest count with rho^(K+1) <= solve_tol.
+__global__ void k_kit(DevSys s) {
+  if (threadIdx.x != 0) return;
+  const double rho = (double)__uint_as_float(*s.rho_bits) * (1.0 + 1e-6);
+  *s.rho_bits = 0u;                  // reset for the next evaluation
+  int K = 1;
+  double err = rho * rho;
+  while (err > s.solve_tol && K < 64) { err *= rho; ++K; }
+  if (s.kit_fixed <= 0) *s.kit = K;
+  if (s.kit_fixed <= 0 && (err > s.solve_tol || rho >= 0.5)) atomicOr(s.status, (int)STATUS_NOTCONV);
+}
+
+// (dt/2) * 2 pi d_j(t_{k+1/2}) for every step; B_s(t) = B(t/dtau + 1/2 - s); and the
+// per-step contraction bound nu_L sum_j |c'_j| maximised into rho_bits.
+template <typename T>
+__global__ __launch_bounds__(256) void k_controls(DevSys s) {
+  using V2 = typename C2<T>::type;
+  __shared__ float smax[256];
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  float rho = 0.f;
+  if (k < s.NT) {
+    const double t = (k + 0.5) * s.dt;
+    const double x = t / s.dtau + 0.5;
+    const int slo = max(0, (int)ceil(x - 1.5)), shi = min(s.d1 - 1, (int)floor(x + 1.5));
+    const double scale = M_PI * s.dt;   // (dt/2) * 2 pi
+    V2 *out = reinterpret_cast<V2 *>(s.ctrl) + k * s.q;
+    double bound = 0.0;
+    for (int j = 0; j < s.q; ++j) {
+      double dre = 0.0, dim = 0.0;
+      for (int f = 0; f < s.nf; ++f) {
+        double er = 0.0, ei = 0.0;
+        const double *a = s.alpha + (size_t)(j * s.nf + f) * 2 * s.d1;
+        for (int sp = slo; sp <= shi; ++sp) {
+          const double b = bspline2(x - sp);
+          er += a[sp] * b;
+          ei += a[s.d1 + sp] * b;
+        }
+        double sn, cs;
+        sincos(s.carrier[j * s.nf + f] * t, &sn, &cs);
+        dre += er * cs - ei * sn;
+        dim += er * sn + ei * cs;
+      }
+      out[j] = V2{(T)(scale * dre), (T)(scale * dim)};
+      bound += scale * sqrt(dre * dre + dim * dim);
+    }
+    rho = (float)(bound * s.nu_L);
+  }
+  smax[threadIdx.x] = rho;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) smax[threadIdx.x] = fmaxf(smax[threadIdx.x], smax[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(s.rho_bits, __float_as_uint(smax[0]));   // nonnegative floats order as integers
+}
+
+template <int NT_>
+__device__ double block_sum(double v, double *sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+#pragma unroll
+  for (int w = NT_ / 2; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Per window: |U^m - W^m|_F^2 (m < M) or |U^M|_F^2 and gamma = <V, U^M>_F (m = M), in FP64.
+__global__ __launch_bounds__(256) void k_boundary_partial(DevSys s) {
+  __shared__ double sh[256];
+  const int m = blockIdx.x;
+  const size_t n = (size_t)s.E * s.N;
+  const double2 *u = reinterpret_cast<const double2 *>(s.Ufin) + (size_t)m * n;
+  double a = 0.0, b = 0.0, c = 0.0;
+  if (m < s.M - 1) {
+    const double2 *w = reinterpret_cast<const double2 *>(s.W) + (size_t)m * n;
+    for (size_t i = threadIdx.x; i < n; i += 256) {
+      const double dr = u[i].x - w[i].x, di = u[i].y - w[i].y;
+      a += dr * dr + di * di;
+    }
+  } else {
+    const double2 *V = reinterpret_cast<const double2 *>(s.V);
+    for (size_t i = threadIdx.x; i < n; i += 256) {
+      const double ur = u[i].x, ui = u[i].y, vr = V[i].x, vi = V[i].y;
+      a += ur * ur + ui * ui;
+      b += vr * ur + vi * ui;   // conj(v) u
+      c += vr * ui - vi * ur;
+    }
+  }
+  a = block_sum<256>(a, sh);
+  b = block_sum<256>(b, sh);
+  c = block_sum<256>(c, sh);
+  if (threadIdx.x == 0) {
+    s.partials[4 * m + 0] = a;
+    s.partials[4 * m + 1] = b;
+    s.partials[4 * m + 2] = c;
+  }
+}
+
+__global__ void k_boundary_final(DevSys s) {
+  if (threadIdx.x != 0) return;
+  double pen = 0.0;
+  for (int m = 0; m < s.M - 1; ++m) {
+    pen += s.partials[4 * m];
+    s.scal[6 + m] = s.partials[4 * m];
+  }
+  const double E = (double)s.E;
+  const double nrm = s.partials[4 * (s.M - 1)], gr = s.partials[4 * (s.M - 1) + 1], gi = s.partials[4 * (s.M - 1) + 2];
+  const double J = nrm / E - (gr * gr + gi * gi) / (E * E);
+  pen *= 0.5 * s.mu;
+  s.scal[0] = J + pen;
+  s.scal[1] = J;
+  s.scal[2] = pen;
+  s.scal[3] = nrm;
+  s.scal[4] = gr;
+  s.scal[5] = gi;
+}
+
+// xy[k] = sum over the window's column groups of the per-wavefront series.
+__global__ void k_series_reduce(DevSys s) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= s.NT) return;
+  const int m = (int)(((k + 1) * s.M - 1) / s.NT);   // window of step k under the floor split
+  const long long kk = k - s.kstart[m];
+  const int w = 2 * s.q;
+  for (int i = 0; i < w; ++i) {
+    double acc = 0.0;
+    for (int cg = 0; cg < s.ncg; ++cg) acc += s.series[(((size_t)m * s.ncg + cg) * s.maxlen + kk) * w + i];
+    s.xy[(size_t)k * w + i] = acc;
+  }
+}
+
+// dP/dalpha for one (qubit j, carrier f, spline s): with X = -2 dt 2 pi Im<y,(a+a^+)z>,
+// Y = -2 dt 2 pi Re<y,(a-a^+)z> per step,
+//   dP/dalpha1 = sum_k B_s(t_k) (cos(W t_k) X_k + sin(W t_k) Y_k),
+//   dP/dalpha2 = sum_k B_s(t_k) (-sin(W t_k) X_k + cos(W t_k) Y_k).
+__global__ __launch_bounds__(256) void k_project(DevSys s) {
+  __shared__ double sh[256];
+  const int b = blockIdx.x;
+  const int sp = b % s.d1, jf = b / s.d1, j = jf / s.nf;
+  const double om = s.carrier[jf];
+  const double r = s.dtau / s.dt;
+  const long long klo = max(0LL, (long long)floor((sp - 2.0) * r - 0.5));
+  const long long khi = min(s.NT - 1, (long long)ceil((sp + 1.0) * r - 0.5));
+  double a1 = 0.0, a2 = 0.0;
+  for (long long k = klo + threadIdx.x; k <= khi; k += 256) {
+    const double t = (k + 0.5) * s.dt;
+    const double bs = bspline2(t / s.dtau + 0.5 - sp);
+    if (bs == 0.0) continue;
+    double sn, cs;
+    sincos(om * t, &sn, &cs);
+    const double s1 = s.xy[(size_t)k * 2 * s.q + 2 * j], s2 = s.xy[(size_t)k * 2 * s.q + 2 * j + 1];
+    a1 += bs * (cs * s1 + sn * s2);
+    a2 += bs * (-sn * s1 + cs * s2);
+  }
+  a1 = block_sum<256>(a1, sh);
+  a2 = block_sum<256>(a2, sh);
+  if (threadIdx.x == 0) {
+    const double fac = -4.0 * M_PI * s.dt;
+    s.grad_alpha[((size_t)jf * 2 + 0) * s.d1 + sp] = fac * a1;
+    s.grad_alpha[((size_t)jf * 2 + 1) * s.d1 + sp] = fac * a2;
+  }
+}
+
+// dP/dW^m = mu (W^m - U^m(t_m)) - 2 Lambda^{m+1}(t_m).  For m = M-1 the backward sweep
+// propagated only gamma V/E^2 of the last window's terminal condition; the dropped part
+// -U^M/E equals -W^{M-1}/E at t_{M-1}, which adds (2/E) W^{M-1} here.
+__global__ void k_grad_W(DevSys s) {
+  const size_t n = (size_t)s.E * s.N;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)(s.M - 1) * n) return;
+  const size_t m = idx / n, rest = idx % n;       // window m+1 (1-based) ends at t_{m+1}
+  const double2 u = reinterpret_cast<const double2 *>(s.Ufin)[m * n + rest];
+  const double2 l = reinterpret_cast<const double2 *>(s.lam0)[(m + 1) * n + rest];
+  const double2 w = reinterpret_cast<const double2 *>(s.W)[idx];
+  const double extra = (m + 2 == (size_t)s.M) ? 2.0 / (double)s.E : 0.0;
+  s.grad_W[2 * idx] = s.mu * (w.x - u.x) - 2.0 * l.x + extra * w.x;
+  s.grad_W[2 * idx + 1] = s.mu * (w.y - u.y) - 2.0 * l.y + extra * w.y;
+}
+
+// ---------------------------------------------------------------------------- dispatch
+
+struct Kernels {
+  void (*fwd)(DevSys, double *, double *, int);
+  void (*roll)(DevSys, double *, double *, int);
+  void (*bwd)(DevSys, int);
+};
+
+template <typename T, int Q, int L, int LD>
+Kernels make() {
+  return Kernels{k_forward<T, Q, L, LD, false>, k_forward<T, Q, L, LD, true>, k_backward<T, Q, L, LD>};
+}
+
+// (q, L) -> lane digits, chosen so that each lane holds at most four entries
+// per state (the backward sweep keeps 16 such arrays live).
+#define QOC_SHAPES(X)   \
+  X(1, 2, 0) X(1, 3, 0) X(1, 4, 0) \
+  X(2, 2, 0) X(2, 3, 1) X(2, 4, 1) \
+  X(3, 2, 1) X(3, 3, 2) X(3, 4, 2) \
+  X(4, 2, 2) X(4, 3, 3) X(4, 4, 3) \
+  X(5, 2, 3) X(6, 2, 4)
+
+template <typename T>
+bool lookup(int q, int L, Kernels *k, int *ld, int *cpw) {
+#define X(Q_, L_, LD_)                                                 \
+  if (q == Q_ && L == L_) {                                            \
+    if (k) *k = make<T, Q_, L_, LD_>();                                \
+    *ld = LD_;                                                         \
+    *cpw = Geo<T, Q_, L_, LD_>::CPW;                                   \
+    return true;                                                       \
+  }
+  QOC_SHAPES(X)
+#undef X
+  return false;
+}
+
+int grid8(int n) { return (n + 7) / 8 * 8; }
+
+template <typename T>
+int phase_T(const DevSys &s, int phase, hipStream_t st, double *Wout, double *Ufinal) {
+  Kernels K;
+  int ld, cpw;
+  if (!lookup<T>(s.q, s.L, &K, &ld, &cpw)) return (int)hipErrorInvalidValue;
+  const int nitems = s.M * s.ncg;
+  switch (phase) {
+    case PHASE_CONTROLS:
+      hipLaunchKernelGGL(k_controls<T>, dim3((unsigned)((s.NT + 255) / 256)), dim3(256), 0, st, s);
+      hipLaunchKernelGGL(k_kit, dim3(1), dim3(64), 0, st, s);
+      break;
+    case PHASE_FORWARD:
+      hipLaunchKernelGGL(K.fwd, dim3(grid8(nitems)), dim3(64), 0, st, s, (double *)nullptr, (double *)nullptr, nitems);
+      break;
+    case PHASE_BOUNDARY:
+      hipLaunchKernelGGL(k_boundary_partial, dim3(s.M), dim3(256), 0, st, s);
+      hipLaunchKernelGGL(k_boundary_final, dim3(1), dim3(64), 0, st, s);
+      break;
+    case PHASE_BACKWARD:
+      hipLaunchKernelGGL(K.bwd, dim3(grid8(nitems)), dim3(64), 0, st, s, nitems);
+      break;
+    case PHASE_PROJECT:
+      hipLaunchKernelGGL(k_series_reduce, dim3((unsigned)((s.NT + 255) / 256)), dim3(256), 0, st, s);
+      hipLaunchKernelGGL(k_project, dim3(s.q * s.nf * s.d1), dim3(256), 0, st, s);
+      break;
+    case PHASE_GRAD_W:
+      if (s.M > 1) {
+        const size_t n = (size_t)(s.M - 1) * s.E * s.N;
+        hipLaunchKernelGGL(k_grad_W, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s);
+      }
+      break;
+    case PHASE_ROLLOUT:
+      hipLaunchKernelGGL(K.roll, dim3(grid8(s.ncg)), dim3(64), 0, st, s, Wout, Ufinal, s.ncg);
+      break;
+    default:
+      return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
+
+}  // namespace
+
+bool layout_for(int q, int L, int fp64, int *ld, int *cpw) {
+  return fp64 ? lookup<double>(q, L, nullptr, ld, cpw) : lookup<float>(q, L, nullptr, ld, cpw);
+}
+
+int launch_phase(const DevSys &s, int phase, hipStream_t st, double *Wout, double *Ufinal) {
+  return s.fp64 ? phase_T<double>(s, phase, st, Wout, Ufinal) : phase_T<float>(s, phase, st, Wout, Ufinal);
+}
+
+}  // namespace qoc

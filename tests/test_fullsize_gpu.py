@@ -1,0 +1,154 @@
+"""Full-size parity: the three configured systems at their real sizes, in the launch
+configuration the benchmark times.
+
+  2 qubits x 3 levels, N_T=4000, M=4      FP64 and FP32 vs the oracle's full gradient
+  3 qubits x 4 levels, N_T=20000, M=32     FP64 and FP32 vs the oracle's full gradient (QR window states)
+  4 qubits x 4 levels, N_T=100000, M=128   objective, per-window penalties and the whole gradient vs the
+                                           oracle; central differences (h=1e-6, 20 directions) on the
+                                           FP64 path; the autograd.Function gradient equals the C-ABI one.
+"""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2407_13950_amd import qoc, workloads as WL
+from paper_2407_13950_amd.autograd import penalty_objective
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def flat(ga, gW):
+    return np.concatenate([ga, np.asarray(gW).view(np.float64).ravel()])
+
+
+def gpu_gradient(w, alpha, W, precision):
+    s = qoc.System(w, precision=precision)
+    s.set_controls(torch.tensor(alpha, device="cuda"))
+    s.set_window_states(torch.tensor(W, device="cuda"))
+    P, terms, ga, gW = s.gradient(device=True)
+    torch.cuda.synchronize()
+    out = float(P.item()), terms.cpu().numpy(), ga.cpu().numpy(), gW.cpu().numpy()
+    s.close()
+    return out
+
+
+def report(name, prec, P, P0, ga, ga0, gW, gW0):
+    e = {"P": abs(P - P0) / abs(P0), "grad": rel(flat(ga, gW), flat(ga0, gW0)), "alpha": rel(ga, ga0),
+         "W": rel(gW, gW0)}
+    print(f"{name} {prec}: P rel {e['P']:.2e}  grad rel-L2 {e['grad']:.2e}  (alpha {e['alpha']:.2e}, W {e['W']:.2e})",
+          flush=True)
+    return e
+
+
+@pytest.mark.parametrize("mk", [WL.c1, WL.c2])
+def test_small_configs_full_size(mk):
+    w = mk()
+    alpha = WL.gen_alpha(w, 11)
+    if w.window_states == "qr":
+        W = WL.gen_qr_states(w, 11)
+    else:
+        Wt, _ = O.rollout(w, alpha)
+        W = Wt + WL.gen_noise(w, 11)
+    t0 = time.time()
+    P0, t0_, ga0, gW0 = O.gradient(w, alpha, W)
+    print(f"{w.name}: oracle gradient {time.time() - t0:.1f} s", flush=True)
+    for prec in ("fp64", "fp32"):
+        P, terms, ga, gW = gpu_gradient(w, alpha, W, prec)
+        e = report(w.name, prec, P, P0, ga, ga0, gW, gW0)
+        if prec == "fp64":
+            assert e["P"] <= 1e-11 and e["grad"] <= 1e-10
+            assert np.allclose(terms, t0_, rtol=1e-10, atol=1e-14)
+        else:
+            assert e["P"] <= 1e-5 and e["grad"] <= 1e-4
+
+
+@pytest.fixture(scope="module")
+def c3_problem():
+    w = WL.c3()
+    alpha = WL.gen_alpha(w, 5)
+    t0 = time.time()
+    Wt, _ = O.rollout(w, alpha)
+    W = Wt + WL.gen_noise(w, 5)
+    print(f"\nC3 oracle roll-out {time.time() - t0:.1f} s", flush=True)
+    t0 = time.time()
+    ref = O.gradient(w, alpha, W)
+    print(f"C3 oracle gradient {time.time() - t0:.1f} s", flush=True)
+    return w, alpha, W, ref
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c3_full_size_matches_oracle(c3_problem, prec):
+    w, alpha, W, (P0, t0, ga0, gW0) = c3_problem
+    P, terms, ga, gW = gpu_gradient(w, alpha, W, prec)
+    e = report(w.name, prec, P, P0, ga, ga0, gW, gW0)
+    pen_rel = np.max(np.abs(terms[4:] - t0[4:]) / np.abs(t0[4:]))
+    print(f"  per-window penalty max rel err {pen_rel:.2e}", flush=True)
+    if prec == "fp64":
+        assert e["P"] <= 1e-11 and e["grad"] <= 1e-10 and pen_rel <= 1e-9
+    else:
+        assert e["P"] <= 1e-5 and e["grad"] <= 1e-4 and pen_rel <= 1e-3
+
+
+def test_c3_sampled_windows_match_oracle_pieces(c3_problem):
+    """Per-window pieces at full size: |C^m|^2 and dP/dW^m for m in {1, 64, 127} from window-local oracle runs."""
+    w, alpha, W, _ = c3_problem
+    P, terms, ga, gW = gpu_gradient(w, alpha, W, "fp64")
+    for m in (1, 64, 127):
+        piece = O.windows(w, alpha, W, m, m + 1)
+        assert abs(terms[4 + m] - piece["pen"][0]) <= 1e-10 * piece["pen"][0]
+        g_ref = w.mu * (W[m - 1] - piece["Ufin"][0]) - 2 * piece["lam0"][1]
+        assert rel(gW[m - 1], g_ref) <= 1e-10
+
+
+def test_c3_central_differences_fp64():
+    """20 random unit directions over (alpha, Re W, Im W), h = 1e-6, on the FP64 path."""
+    w = WL.c3()
+    alpha = WL.gen_alpha(w, 9)
+    s = qoc.System(w, precision="fp64")
+    s.set_controls(alpha)
+    Wr, _ = s.rollout()
+    W = Wr + WL.gen_noise(w, 9)
+    s.set_window_states(W)
+    P, terms, ga, gW = s.gradient()
+    gnorm = np.linalg.norm(flat(ga, gW))
+    h = 1e-6
+    worst = 0.0
+    for v in WL.gen_directions(w, 10, 20):
+        s.set_controls(alpha + h * v["alpha"])
+        s.set_window_states(W + h * v["W"])
+        Pp, _ = s.objective()
+        s.set_controls(alpha - h * v["alpha"])
+        s.set_window_states(W - h * v["W"])
+        Pm, _ = s.objective()
+        fd = (Pp - Pm) / (2 * h)
+        an = float(ga @ v["alpha"] + np.sum(gW.real * v["W"].real + gW.imag * v["W"].imag))
+        worst = max(worst, abs(fd - an) / (abs(an) + 1e-3 * gnorm))
+    print(f"C3 FD worst scaled error {worst:.2e} (|grad| = {gnorm:.3e})", flush=True)
+    assert worst <= 1e-5
+
+
+def test_c3_autograd_function_matches_c_abi():
+    w = WL.c3()
+    alpha = WL.gen_alpha(w, 3)
+    W = WL.gen_qr_states(w, 3)
+    s = qoc.System(w, precision="fp32")
+    a = torch.tensor(alpha, device="cuda", requires_grad=True)
+    Wt = torch.tensor(W, device="cuda", requires_grad=True)
+    P = penalty_objective(a, Wt, s)
+    (2.5 * P).backward()
+    s2 = qoc.System(w, precision="fp32")
+    s2.set_controls(alpha)
+    s2.set_window_states(W)
+    P2, _, ga2, gW2 = s2.gradient()
+    assert float(P.item()) == P2
+    assert np.array_equal(a.grad.cpu().numpy(), 2.5 * ga2)
+    assert np.array_equal(Wt.grad.cpu().numpy(), 2.5 * gW2)

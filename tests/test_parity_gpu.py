@@ -1,0 +1,172 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances (derived in the design doc):
+  FP64 propagation: P and terms to 1e-11 relative, gradients to 1e-10 in
+  relative L2 (fixed-point truncation <= 2^-54 per step plus rounding-order
+  differences over <= 1e5 steps).
+  FP32 propagation with FP64 reductions: objective 1e-5 relative, whole gradient
+  1e-4 relative L2 (the stated targets); the alpha and W parts are reported and
+  bounded separately.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2407_13950_amd import qoc, workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def small_case(q, L, n_steps, M, seed=1, d1=None, T=None, nf=None, states="rollout", ckpt=0):
+    base = {2: WL.c1, 3: WL.c2, 4: WL.c3}.get(q)
+    if base is not None:
+        w = base()
+    else:
+        rng = np.random.default_rng(q)
+        E = 2 ** q
+        w = WL.Workload(name=f"q{q}", q=q, L=L, T=100.0, n_steps=1000, n_windows=4, n_splines=10, mu=2.0 / E,
+                        detuning=rng.uniform(-0.5, 0.5, q), anharmonicity=np.full(q, -1.2),
+                        cross_kerr=np.full(max(q - 1, 0), 0.03), carriers=rng.uniform(-0.6, 0.6, (q, 2)),
+                        target=WL.qft_target(E))
+    if nf is not None:
+        w = w.replace(carriers=w.carriers[:, :nf])
+    Tn = T if T is not None else w.T * n_steps / w.n_steps * (4 if q >= 3 else 1)
+    w = w.replace(L=L, n_steps=n_steps, n_windows=M, T=Tn, n_splines=d1 or max(4, min(w.n_splines, 8)),
+                  checkpoint_every=ckpt, name=f"q{q}L{L}-NT{n_steps}-M{M}")
+    alpha = WL.gen_alpha(w, seed)
+    if M == 1:
+        W = None
+    elif states == "rollout":
+        Wt, _ = O.rollout(w, alpha)
+        W = Wt + WL.gen_noise(w, seed)
+    else:
+        W = WL.gen_qr_states(w, seed)
+    return w, alpha, W
+
+
+def run_gpu(w, alpha, W, precision, device=True, **kw):
+    s = qoc.System(w, precision=precision, **kw)
+    if device:
+        s.set_controls(torch.tensor(alpha, device="cuda"))
+        if W is not None:
+            s.set_window_states(torch.tensor(W, device="cuda"))
+        else:
+            s.set_window_states(None)
+        P, terms, ga, gW = s.gradient(device=True)
+        torch.cuda.synchronize()
+        out = (float(P.item()), terms.cpu().numpy(), ga.cpu().numpy(), gW.cpu().numpy())
+    else:
+        s.set_controls(alpha)
+        s.set_window_states(W if W is not None else None)
+        out = s.gradient(device=False)
+    s.close()
+    return out
+
+
+CASES = [
+    # q, L, n_steps, M          -- several windows, ragged splits, every kernel instance family
+    (2, 3, 400, 4), (2, 3, 403, 5), (3, 4, 300, 7), (4, 4, 240, 6), (2, 2, 200, 3), (2, 4, 210, 4),
+    (3, 2, 150, 5), (3, 3, 180, 4), (4, 2, 160, 4), (4, 3, 120, 3), (1, 3, 100, 3), (5, 2, 120, 3),
+    (6, 2, 90, 2), (2, 3, 300, 1), (2, 3, 8, 8),
+]
+
+
+@pytest.mark.parametrize("q,L,n_steps,M", CASES)
+def test_fp64_matches_oracle(q, L, n_steps, M):
+    w, alpha, W = small_case(q, L, n_steps, M)
+    P0, t0, ga0, gW0 = O.gradient(w, alpha, W)
+    P, t, ga, gW = run_gpu(w, alpha, W, "fp64")
+    print(f"{w.name}: P={P:.15g} oracle={P0:.15g}", flush=True)
+    assert abs(P - P0) <= 1e-11 * abs(P0)
+    assert np.allclose(t, t0, rtol=1e-10, atol=1e-14)
+    assert rel(ga, ga0) <= 1e-10
+    if M > 1:
+        assert rel(gW, gW0) <= 1e-10
+
+
+@pytest.mark.parametrize("q,L,n_steps,M", CASES)
+def test_fp32_matches_oracle(q, L, n_steps, M):
+    w, alpha, W = small_case(q, L, n_steps, M)
+    P0, t0, ga0, gW0 = O.gradient(w, alpha, W)
+    P, t, ga, gW = run_gpu(w, alpha, W, "fp32")
+    full = rel(np.concatenate([ga, gW.view(np.float64).ravel()]), np.concatenate([ga0, gW0.view(np.float64).ravel()]))
+    print(f"{w.name}: P rel {abs(P - P0) / abs(P0):.2e}  grad rel-L2 {full:.2e}  alpha {rel(ga, ga0):.2e}"
+          + (f"  W {rel(gW, gW0):.2e}" if M > 1 else ""), flush=True)
+    assert abs(P - P0) <= 1e-5 * abs(P0)
+    assert full <= 1e-4
+    assert rel(ga, ga0) <= 1e-4
+
+
+def test_checkpoint_resync_matches_oracle():
+    """Checkpoints every 7 steps inside 50-step windows: the reverse reconstruction re-syncs there."""
+    w, alpha, W = small_case(3, 4, 200, 4, ckpt=7)
+    P0, t0, ga0, gW0 = O.gradient(w, alpha, W)
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-4)):
+        P, t, ga, gW = run_gpu(w, alpha, W, prec)
+        assert rel(ga, ga0) <= tol and rel(gW, gW0) <= tol * 10
+
+
+def test_host_and_device_buffers_agree_bitwise():
+    w, alpha, W = small_case(3, 4, 200, 5)
+    a = run_gpu(w, alpha, W, "fp32", device=True)
+    b = run_gpu(w, alpha, W, "fp32", device=False)
+    assert a[0] == b[0]
+    for x, y in zip(a[1:], b[1:]):
+        assert np.array_equal(x, y)
+
+
+def test_repeatable_bitwise():
+    w, alpha, W = small_case(4, 4, 160, 4)
+    a = run_gpu(w, alpha, W, "fp32")
+    b = run_gpu(w, alpha, W, "fp32")
+    assert a[0] == b[0] and all(np.array_equal(x, y) for x, y in zip(a[1:], b[1:]))
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 3e-6)])
+def test_rollout_matches_oracle(prec, tol):
+    w, alpha, _ = small_case(3, 4, 400, 6)
+    Wt0, U0 = O.rollout(w, alpha)
+    s = qoc.System(w, precision=prec)
+    s.set_controls(alpha)
+    Wt, U = s.rollout()
+    assert rel(Wt, Wt0) <= tol and rel(U, U0) <= tol
+    # the objective at the roll-out states has no penalty up to propagation rounding
+    s.set_window_states(Wt)
+    P, terms = s.objective()
+    assert terms[1] <= (1e-20 if prec == "fp64" else 1e-9)
+
+
+def test_objective_only_matches_gradient_call():
+    w, alpha, W = small_case(2, 3, 400, 4)
+    s = qoc.System(w, precision="fp32")
+    s.set_controls(alpha)
+    s.set_window_states(W)
+    P1, t1 = s.objective()
+    P2, t2, _, _ = s.gradient()
+    assert P1 == P2 and np.array_equal(t1, t2)
+
+
+def test_fixed_iteration_override_and_convergence_flag():
+    """Controls far too strong for dt: the contraction bound fails and the call reports it."""
+    w, alpha, W = small_case(2, 3, 40, 2)
+    s = qoc.System(w, precision="fp64")
+    s.set_controls(alpha * 400.0)
+    s.set_window_states(W)
+    with pytest.raises(qoc.QocError) as e:
+        s.objective()
+    assert e.value.code == qoc.QOC_ENOTCONV
+    s.close()
+    s = qoc.System(w, precision="fp64", fixed_point_iters=30)   # caller-forced count: no bound check
+    s.set_controls(alpha)
+    s.set_window_states(W)
+    P, _ = s.objective()
+    P0, _ = O.objective(w, alpha, W)
+    assert abs(P - P0) <= 1e-12 * abs(P0)
