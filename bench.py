@@ -74,6 +74,84 @@ def cpu_baseline(w, alpha, seconds):
             "seconds_per_eval": per_eval}
 
 
+def bench_batch(seed, reps, log):
+    """The batched mix: 64 evaluations (32/24/8 of the 2/3/4-qubit systems, windows in
+    {4,16,64,128}) per qoc_batch_run, FP32 propagation with FP64 accumulation."""
+    import numpy as np
+    import torch
+    from paper_2407_13950_amd import qoc, workloads as WL
+    mix = WL.batch_mix(seed)
+    systems, members = [], []
+    for e in mix:
+        w = e["workload"]
+        s = qoc.System(w, precision="fp32")
+        s.set_controls(torch.tensor(WL.gen_alpha(w, e["seed"]), device="cuda"))
+        s.set_window_states(torch.tensor(WL.gen_qr_states(w, e["seed"]), device="cuda"))
+        systems.append(s)
+        members.append(w)
+    b = qoc.Batch(max_contexts=64, max_items=400000)
+    b.run(systems)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.run(systems)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # batched results equal solo results bit for bit (spot check over all three shapes)
+    same = True
+    for idx in (0, 40, 63):
+        P_b, _, ga_b, _ = systems[idx].read_results()
+        s2 = qoc.System(members[idx], precision="fp32")
+        e = mix[idx]
+        s2.set_controls(WL.gen_alpha(members[idx], e["seed"]))
+        s2.set_window_states(WL.gen_qr_states(members[idx], e["seed"]))
+        P_s, _, ga_s, _ = s2.gradient()
+        same &= (P_b == P_s) and bool(np.array_equal(ga_b, ga_s))
+        s2.close()
+    evals = 64 * reps
+    wsteps = sum(2 * w.n_steps for w in members) * reps
+    out = {"evals_per_s": evals / el, "window_steps_per_s": wsteps / el, "ms_per_batch": 1e3 * el / reps,
+           "batch": "32x(q2,L3,N_T=4000) + 24x(q3,L4,N_T=20000) + 8x(q4,L4,N_T=100000), M in {4,16,64,128}",
+           "reps": reps, "equal_to_solo_bitwise": bool(same)}
+    log(f"batched mix: {out['evals_per_s']:.1f} evals/s, {out['ms_per_batch']:.1f} ms per 64-eval batch")
+    for s in systems:
+        s.close()
+    return out
+
+
+def bench_serve(rate, n_requests, plain_requests, seed, budget_gb, log):
+    """Open-loop Poisson trace through the continuous-batching server, and the plain FP64
+    per-request path on the first `plain_requests` requests of the same trace."""
+    import numpy as np
+    from paper_2407_13950_amd import serve
+    out = {"rate_rps": rate, "requests": n_requests, "runs": 64, "objective_only": 0.1,
+           "hbm_budget_GB": budget_gb}
+    runs, reqs, counts = serve.make_trace(n_requests, rate=rate, seed=seed, n_runs=64)
+    be = serve.QocBackend(precision="fp32", n_streams=2, max_batch=64, max_items=400000)
+    srv = serve.Server(be, hbm_budget=int(budget_gb * (1 << 30)), max_batch=64)
+    for r, w in runs.items():
+        srv.register_run(r, w, counts[r], initial=serve.initial_inputs(w, 1000 + r))
+    summ = srv.run_trace(reqs, progress=lambda d, n: log(f"serve: {d}/{n} done"))
+    out["batched_fp32"] = dict(summ, batches=srv.batches, mean_batch=float(np.mean(srv.batch_sizes)),
+                               peak_hbm_GB=srv.peak_used / (1 << 30))
+    log(f"serve fp32: {summ['throughput_rps']:.1f} req/s p50 {summ['p50_ms']:.2f} ms p99 {summ['p99_ms']:.2f} ms")
+    if plain_requests > 0:
+        runs, reqs, counts = serve.make_trace(n_requests, rate=rate, seed=seed, n_runs=64)
+        reqs = reqs[:plain_requests]
+        cnt = {r: 0 for r in runs}
+        for q in reqs:
+            cnt[q.run_id] += 1
+        srv = serve.Server(serve.PlainBackend("fp64"), hbm_budget=int(budget_gb * (1 << 30)), max_batch=1)
+        for r, w in runs.items():
+            if cnt[r]:
+                srv.register_run(r, w, cnt[r], initial=serve.initial_inputs(w, 1000 + r))
+        summ = srv.run_trace(reqs, progress=lambda d, n: log(f"plain fp64: {d}/{n} done"))
+        out["plain_fp64_per_request"] = dict(summ, note=f"first {plain_requests} requests of the same trace")
+        log(f"serve plain fp64: {summ['throughput_rps']:.1f} req/s p50 {summ['p50_ms']:.2f} ms "
+            f"p99 {summ['p99_ms']:.2f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +161,12 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=3, help="steps of the plain FP64 form timed for comparison")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU-oracle sample size (0: skip)")
     ap.add_argument("--seed", type=int, default=2024)
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched-mix and serving measurements")
+    ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--serve-plain-requests", type=int, default=600)
+    ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate as a fraction of the batched mix rate")
+    ap.add_argument("--hbm-budget-gb", type=float, default=6.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -200,6 +284,16 @@ def main():
                                 "phases_ms": {k: t64[k] for k in qoc.PHASES}}
         s64.close()
         log(f"fp64 plain form: {args.fp64_steps / e64:.2f} evals/s")
+
+    if not args.no_extras:
+        try:
+            result["batched_mix"] = bench_batch(args.seed, args.batch_reps, log)
+            rate = args.serve_load * result["batched_mix"]["evals_per_s"]
+            result["serving"] = bench_serve(rate, args.serve_requests, args.serve_plain_requests, args.seed,
+                                            args.hbm_budget_gb, log)
+        except Exception as e:   # the headline line must still be printed
+            result["extras_error"] = repr(e)
+            log(f"extras failed: {e!r}")
 
     if args.cpu_seconds > 0:
         result["cpu_baseline"] = cpu_baseline(w, alpha_np, args.cpu_seconds)

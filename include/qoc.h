@@ -151,6 +151,34 @@ int qoc_backward(qoc_ctx *ctx, double *grad_alpha, double *grad_W, int32_t where
  * of W; U_out (nullable): U(T), 2*N*E doubles.  Both share `where`. */
 int qoc_rollout(qoc_ctx *ctx, double *W_out, double *U_out, int32_t where);
 
+/* ---- Batched evaluation of several contexts (many systems, one launch per phase).
+ *
+ * A batch object owns the device tables that describe one batched launch
+ * sequence; create one per stream that runs batches.  qoc_batch_run evaluates
+ * every listed context with its current controls and window states: all
+ * (context, window, column group) propagation items of all contexts form one
+ * forward launch and one backward launch, ordered longest first; the small FP64
+ * kernels run as one launch each over all contexts.  Each context's results
+ * stay in its own buffers (read them with qoc_read_results).  All contexts must
+ * share the batch's device and one precision and appear at most once; a context
+ * must not be used on another stream while the batch runs.  want_grad (nullable:
+ * all) selects objective-only (0) or objective+gradient (1) per context.  Each
+ * context's stream becomes `hip_stream`.  The call is asynchronous.  Errors:
+ * QOC_EINVAL (mixed precision/device, duplicates, more contexts or items than
+ * the batch was created for), QOC_ESTATE (a context without controls/states).
+ * Results agree with the single-context calls bit for bit (same kernels, same
+ * reduction order). */
+typedef struct qoc_batch qoc_batch;
+int qoc_batch_create(int32_t device, int32_t max_contexts, int64_t max_items, qoc_batch **out);
+int qoc_batch_destroy(qoc_batch *b);
+int qoc_batch_run(qoc_batch *b, qoc_ctx *const *ctxs, int32_t n, const int32_t *want_grad, void *hip_stream);
+
+/* Results of the last evaluation of ctx (single or batched) into caller buffers
+ * (all nullable; layouts as in qoc_gradient; gradients only after a gradient
+ * evaluation, else QOC_ESTATE).  Device outputs are copied on the context's
+ * stream without waiting; host outputs synchronise. */
+int qoc_read_results(qoc_ctx *ctx, double *P, double *terms, double *grad_alpha, double *grad_W, int32_t where);
+
 /* Per-phase kernel timing with HIP events recorded on the context's stream.
  * Phases: 0 controls (+ iteration count), 1 forward sweep, 2 boundary reductions,
  * 3 backward (adjoint) sweep, 4 gradient series reduction + B-spline projection,

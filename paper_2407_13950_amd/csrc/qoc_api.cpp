@@ -64,9 +64,11 @@ struct qoc_ctx {
   long long NT = 0;
   int device = 0;
   int fp64 = 0;
+  int shape = 0;                                   // kernel-instance index of (q, L)
   hipStream_t stream = nullptr;
   bool have_alpha = false, have_W = false;
   bool forward_valid = false;                      // forward sweep matches the current inputs
+  bool grad_valid = false;                         // internal gradient buffers hold the last gradient
   size_t bytes = 0;
   std::vector<void *> allocs;
   double *roll_W = nullptr, *roll_U = nullptr;   // staging for host roll-out outputs
@@ -152,13 +154,14 @@ int qoc_create(const qoc_system_desc *desc, qoc_ctx **out) {
   }
   const int fp64 = D.precision == QOC_FP64;
   int ld = 0, cpw = 1;
-  if (!qoc::layout_for(q, L, fp64, &ld, &cpw))
+  int shape = 0;
+  if (!qoc::layout_for(q, L, fp64, &ld, &cpw, &shape))
     return fail(QOC_EUNSUPPORTED, "no kernel instance for q=" + std::to_string(q) + " L=" + std::to_string(L));
 
   HIP_OR_RETURN(hipSetDevice(D.device));
   qoc_ctx *c = new qoc_ctx();
   c->q = q; c->L = L; c->N = (int)N; c->E = E; c->nf = nf; c->d1 = d1; c->M = M;
-  c->d = 2 * d1 * q * nf; c->NT = NT; c->device = D.device; c->fp64 = fp64;
+  c->d = 2 * d1 * q * nf; c->NT = NT; c->device = D.device; c->fp64 = fp64; c->shape = shape;
 
   // ---- host system build (FP64)
   const double dt = D.T / (double)NT;
@@ -285,6 +288,7 @@ int qoc_set_controls(qoc_ctx *ctx, const double *alpha, int64_t d, int32_t where
   HIP_OR_RETURN(hipMemcpyAsync(const_cast<double *>(ctx->dev.alpha), alpha, sizeof(double) * d, kind_in(where), ctx->stream));
   ctx->have_alpha = true;
   ctx->forward_valid = false;
+  ctx->grad_valid = false;
   return QOC_OK;
 }
 
@@ -300,6 +304,7 @@ int qoc_set_window_states(qoc_ctx *ctx, const double *W, int64_t n_doubles, int3
   HIP_OR_RETURN(hipMemcpyAsync(const_cast<double *>(ctx->dev.W), W, sizeof(double) * need, kind_in(where), ctx->stream));
   ctx->have_W = true;
   ctx->forward_valid = false;
+  ctx->grad_valid = false;
   return QOC_OK;
 }
 
@@ -339,6 +344,7 @@ static int run(qoc_ctx *ctx, int ph0, int ph1, double *P, double *terms, double 
     if (timed) HIP_OR_RETURN(hipEventRecord(ctx->ev(call, ph + 1), ctx->stream));
   }
   if (ph0 == 0) ctx->forward_valid = true;
+  ctx->grad_valid = grad && !(where == QOC_DEVICE);
   if (timed) {
     ctx->call_ph0[call] = (char)ph0;
     ctx->call_ph1[call] = (char)ph1;
@@ -448,6 +454,170 @@ int qoc_rollout(qoc_ctx *ctx, double *W_out, double *U_out, int32_t where) {
     if (U_out) HIP_OR_RETURN(hipMemcpyAsync(U_out, ud, sizeof(double) * nU, hipMemcpyDeviceToHost, ctx->stream));
     return check_status(ctx);
   }
+  return QOC_OK;
+}
+
+
+// ---------------------------------------------------------------------------- batches
+
+struct qoc_batch {
+  int device = 0;
+  int max_ctx = 0;
+  long long max_items = 0;
+  long long max_blocks = 0;
+  qoc::DevSys *d_sys = nullptr;
+  int4 *d_items = nullptr;       // forward items then backward items
+  int2 *d_blocks = nullptr;      // all small-kernel tables
+  char *h_stage = nullptr;       // pinned staging for the uploads
+  size_t stage_bytes = 0;
+  hipEvent_t uploaded = nullptr; // staging may be rewritten once this has passed
+  bool pending = false;
+  ~qoc_batch() {
+    if (uploaded) { (void)hipEventSynchronize(uploaded); (void)hipEventDestroy(uploaded); }
+    (void)hipFree(d_sys); (void)hipFree(d_items); (void)hipFree(d_blocks);
+    (void)hipHostFree(h_stage);
+  }
+};
+
+int qoc_batch_create(int32_t device, int32_t max_contexts, int64_t max_items, qoc_batch **out) {
+  if (!out || max_contexts < 1 || max_items < 1) return fail(QOC_EINVAL, "qoc_batch_create: bad arguments");
+  *out = nullptr;
+  HIP_OR_RETURN(hipSetDevice(device));
+  qoc_batch *b = new qoc_batch();
+  b->device = device;
+  b->max_ctx = max_contexts;
+  b->max_items = max_items;
+  b->max_blocks = 4 * max_items + 1024LL * max_contexts;   // generous: small kernels need few blocks per system
+  b->stage_bytes = sizeof(qoc::DevSys) * max_contexts + sizeof(int4) * 2 * max_items + sizeof(int2) * b->max_blocks;
+  hipError_t e = hipMalloc(&b->d_sys, sizeof(qoc::DevSys) * max_contexts);
+  if (e == hipSuccess) e = hipMalloc(&b->d_items, sizeof(int4) * 2 * max_items);
+  if (e == hipSuccess) e = hipMalloc(&b->d_blocks, sizeof(int2) * b->max_blocks);
+  if (e == hipSuccess) e = hipHostMalloc(&b->h_stage, b->stage_bytes, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming);
+  if (e != hipSuccess) { delete b; return fail(QOC_ENOMEM, std::string("qoc_batch_create: ") + hipGetErrorString(e)); }
+  *out = b;
+  return QOC_OK;
+}
+
+int qoc_batch_destroy(qoc_batch *b) {
+  if (!b) return QOC_OK;
+  (void)hipSetDevice(b->device);
+  delete b;
+  return QOC_OK;
+}
+
+int qoc_batch_run(qoc_batch *b, qoc_ctx *const *ctxs, int32_t n, const int32_t *want_grad, void *hip_stream) {
+  if (!b || !ctxs || n < 1) return fail(QOC_EINVAL, "qoc_batch_run: bad arguments");
+  if (n > b->max_ctx) return fail(QOC_EINVAL, "qoc_batch_run: more contexts than the batch was created for");
+  const int fp64 = ctxs[0] ? ctxs[0]->fp64 : 0;
+  for (int i = 0; i < n; ++i) {
+    qoc_ctx *c = ctxs[i];
+    if (!c) return fail(QOC_EINVAL, "qoc_batch_run: NULL context");
+    if (c->device != b->device) return fail(QOC_EINVAL, "qoc_batch_run: context on another device");
+    if (c->fp64 != fp64) return fail(QOC_EINVAL, "qoc_batch_run: mixed precisions");
+    if (!c->have_alpha || (c->M > 1 && !c->have_W)) return fail(QOC_ESTATE, "qoc_batch_run: context without inputs");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == c) return fail(QOC_EINVAL, "qoc_batch_run: context listed twice");
+  }
+  HIP_OR_RETURN(hipSetDevice(b->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  // propagation items, longest first (cost ~ steps x entries per lane x qubits)
+  struct It { long long cost; int4 v; };
+  std::vector<It> fwd, bwd;
+  long long nblocks = 0;
+  for (int i = 0; i < n; ++i) {
+    const qoc_ctx *c = ctxs[i];
+    const bool g = !want_grad || want_grad[i];
+    const long long per_lane = (long long)c->N / std::max(1, (64 / c->dev.cpw)) + 1;
+    for (int m = 0; m < c->M; ++m) {
+      long long len = 0;
+      // window length from the floor split
+      len = (long long)(((__int128)(m + 1) * c->NT) / c->M) - (long long)(((__int128)m * c->NT) / c->M);
+      for (int cg = 0; cg < c->dev.ncg; ++cg) {
+        const int4 v = make_int4(i, m, cg, c->shape);
+        fwd.push_back({len * per_lane * c->q, v});
+        if (g) bwd.push_back({2 * len * per_lane * c->q, v});
+      }
+    }
+    for (int k = 0; k < qoc::SK_COUNT; ++k) {
+      const bool gk = k == qoc::SK_SERIES || k == qoc::SK_PROJECT || k == qoc::SK_GRADW;
+      if (!gk || g) nblocks += qoc::small_blocks(c->dev, k);
+    }
+  }
+  if ((long long)fwd.size() > b->max_items || (long long)bwd.size() > b->max_items)
+    return fail(QOC_EINVAL, "qoc_batch_run: more propagation items than the batch was created for");
+  if (nblocks > b->max_blocks) return fail(QOC_EINVAL, "qoc_batch_run: small-kernel table exceeds the batch capacity");
+  auto by_cost = [](const It &x, const It &y) { return x.cost > y.cost; };
+  std::stable_sort(fwd.begin(), fwd.end(), by_cost);
+  std::stable_sort(bwd.begin(), bwd.end(), by_cost);
+
+  // the previous run's uploads must have left the staging buffer
+  if (b->pending) HIP_OR_RETURN(hipEventSynchronize(b->uploaded));
+  char *h = b->h_stage;
+  qoc::DevSys *hs = reinterpret_cast<qoc::DevSys *>(h);
+  int4 *hi = reinterpret_cast<int4 *>(h + sizeof(qoc::DevSys) * b->max_ctx);
+  int2 *hb = reinterpret_cast<int2 *>(h + sizeof(qoc::DevSys) * b->max_ctx + sizeof(int4) * 2 * b->max_items);
+  for (int i = 0; i < n; ++i) hs[i] = ctxs[i]->dev;
+  for (size_t k = 0; k < fwd.size(); ++k) hi[k] = fwd[k].v;
+  for (size_t k = 0; k < bwd.size(); ++k) hi[fwd.size() + k] = bwd[k].v;
+  qoc::BatchPlan plan{};
+  plan.fp64 = fp64;
+  plan.sys = b->d_sys;
+  plan.fwd_items = b->d_items;
+  plan.bwd_items = b->d_items + fwd.size();
+  plan.n_fwd = (int)fwd.size();
+  plan.n_bwd = (int)bwd.size();
+  long long off = 0;
+  for (int k = 0; k < qoc::SK_COUNT; ++k) {
+    const bool gk = k == qoc::SK_SERIES || k == qoc::SK_PROJECT || k == qoc::SK_GRADW;
+    plan.blocks[k] = b->d_blocks + off;
+    long long cnt = 0;
+    for (int i = 0; i < n; ++i) {
+      if (gk && want_grad && !want_grad[i]) continue;
+      const int nb = qoc::small_blocks(ctxs[i]->dev, k);
+      for (int j = 0; j < nb; ++j) hb[off + cnt++] = make_int2(i, j);
+    }
+    plan.n_blocks[k] = (int)cnt;
+    off += cnt;
+  }
+  HIP_OR_RETURN(hipMemcpyAsync(b->d_sys, hs, sizeof(qoc::DevSys) * n, hipMemcpyHostToDevice, st));
+  HIP_OR_RETURN(hipMemcpyAsync(b->d_items, hi, sizeof(int4) * (fwd.size() + bwd.size()), hipMemcpyHostToDevice, st));
+  HIP_OR_RETURN(hipMemcpyAsync(b->d_blocks, hb, sizeof(int2) * std::max<long long>(off, 1), hipMemcpyHostToDevice, st));
+  HIP_OR_RETURN(hipEventRecord(b->uploaded, st));
+  b->pending = true;
+  bool any_grad = false;
+  for (int i = 0; i < n; ++i) any_grad |= (!want_grad || want_grad[i]);
+  const int nph = any_grad ? qoc::PHASE_GRAD_W + 1 : qoc::PHASE_BOUNDARY + 1;
+  for (int ph = 0; ph < nph; ++ph) {
+    int e = qoc::launch_batch_phase(plan, ph, st);
+    if (e) {
+      for (int i = 0; i < n; ++i) ctxs[i]->forward_valid = false;
+      return hip_fail((hipError_t)e, "batched kernel launch");
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    qoc_ctx *c = ctxs[i];
+    c->stream = st;
+    c->forward_valid = true;
+    c->grad_valid = !want_grad || want_grad[i];
+  }
+  return QOC_OK;
+}
+
+int qoc_read_results(qoc_ctx *ctx, double *P, double *terms, double *grad_alpha, double *grad_W, int32_t where) {
+  if (!ctx) return fail(QOC_EINVAL, "qoc_read_results: NULL context");
+  if (where != QOC_HOST && where != QOC_DEVICE) return fail(QOC_EINVAL, "qoc_read_results: bad memory kind");
+  if (!ctx->forward_valid) return fail(QOC_ESTATE, "qoc_read_results: no evaluation for the current inputs");
+  if ((grad_alpha || grad_W) && !ctx->grad_valid) return fail(QOC_ESTATE, "qoc_read_results: no gradient evaluated");
+  HIP_OR_RETURN(hipSetDevice(ctx->device));
+  const hipMemcpyKind k = kind_out(where);
+  const qoc::DevSys &s = ctx->dev;
+  if (P) HIP_OR_RETURN(hipMemcpyAsync(P, s.scal, sizeof(double), k, ctx->stream));
+  if (terms) HIP_OR_RETURN(hipMemcpyAsync(terms, s.scal + 1, sizeof(double) * (4 + ctx->M), k, ctx->stream));
+  if (grad_alpha) HIP_OR_RETURN(hipMemcpyAsync(grad_alpha, s.grad_alpha, sizeof(double) * ctx->d, k, ctx->stream));
+  if (grad_W && ctx->M > 1)
+    HIP_OR_RETURN(hipMemcpyAsync(grad_W, s.grad_W, sizeof(double) * 2 * (size_t)(ctx->M - 1) * ctx->E * ctx->N, k, ctx->stream));
+  if (where == QOC_HOST) return check_status(ctx);
   return QOC_OK;
 }
 

@@ -51,9 +51,9 @@ struct DevSys {
 
 enum { STATUS_NOTCONV = 1 };
 
-// Layout chosen for a (q, L) pair: lane digits and columns per wavefront.
-// Returns false when no kernel instance exists for the pair.
-bool layout_for(int q, int L, int fp64, int *ld, int *cpw);
+// Layout chosen for a (q, L) pair: lane digits, columns per wavefront and the
+// kernel-instance index.  Returns false when no kernel instance exists for the pair.
+bool layout_for(int q, int L, int fp64, int *ld, int *cpw, int *shape);
 
 // Phases of one evaluation, launched in this order on one stream:
 // objective = CONTROLS, FORWARD, BOUNDARY; gradient adds BACKWARD, PROJECT, GRAD_W.
@@ -61,7 +61,25 @@ bool layout_for(int q, int L, int fp64, int *ld, int *cpw);
 enum Phase { PHASE_CONTROLS = 0, PHASE_FORWARD, PHASE_BOUNDARY, PHASE_BACKWARD, PHASE_PROJECT, PHASE_GRAD_W,
              PHASE_ROLLOUT, N_PHASES };
 
+// The small FP64 kernels; small_blocks() gives each one's block count for a system.
+enum SmallKind { SK_CONTROLS = 0, SK_KIT, SK_BPARTIAL, SK_BFINAL, SK_SERIES, SK_PROJECT, SK_GRADW, SK_COUNT };
+int small_blocks(const DevSys &s, int kind);
+
 // Returns 0 or a hipError_t value.
 int launch_phase(const DevSys &s, int phase, hipStream_t st, double *Wout = nullptr, double *Ufinal = nullptr);
+
+// Several systems evaluated together: the propagation phases run as one launch
+// over all (system, window, column group) items, each small kernel as one launch
+// over a (system, block) table.  All systems share the precision `fp64`.
+struct BatchPlan {
+  const DevSys *sys;              // [n] device copy of the systems
+  const int4 *fwd_items;          // [n_fwd] (system, window, column group, shape), longest first
+  const int4 *bwd_items;          // [n_bwd]
+  int n_fwd, n_bwd;
+  const int2 *blocks[SK_COUNT];   // per small kernel: (system, block within the system)
+  int n_blocks[SK_COUNT];
+  int fp64;
+};
+int launch_batch_phase(const BatchPlan &p, int phase, hipStream_t st);
 
 }  // namespace qoc

@@ -41,6 +41,23 @@ constexpr int cpow2(int x) { return x <= 1 ? 1 : 2 * cpow2((x + 1) / 2); }
 template <typename T> struct C2 { using type = float2; };
 template <> struct C2<double> { using type = double2; };
 
+// a*b + c as one fused instruction (the compiler would otherwise pair some products
+// with separate adds when expressions combine several products).
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// s += a*v and s += conj(a)*v on split complex values, four fused operations each.
+template <typename T>
+__device__ __forceinline__ void cmac(T &sr, T &si, T ar, T ai, T vr, T vi) {
+  sr = fma_(ar, vr, sr); sr = fma_(-ai, vi, sr);
+  si = fma_(ar, vi, si); si = fma_(ai, vr, si);
+}
+template <typename T>
+__device__ __forceinline__ void cmac_conj(T &sr, T &si, T ar, T ai, T vr, T vi) {
+  sr = fma_(ar, vr, sr); sr = fma_(ai, vi, sr);
+  si = fma_(ar, vi, si); si = fma_(-ai, vr, si);
+}
+
 template <typename T, int Q, int L, int LD>
 struct Geo {
   static constexpr int N = cipow(L, Q);
@@ -152,8 +169,8 @@ struct Lane {
   __device__ __forceinline__ void scale_m1(int e, T ur, T ui, T &xr, T &xi) const {
     const T sg = CONJ ? (T)-1 : (T)1;
     if constexpr (sizeof(T) == 4) {
-      xr = (mrl[e] * ur - sg * mil[e] * ui) + mr[e] * ur - sg * mi[e] * ui;
-      xi = (mrl[e] * ui + sg * mil[e] * ur) + mr[e] * ui + sg * mi[e] * ur;
+      xr = fma_(-sg * mi[e], ui, fma_(mr[e], ur, fma_(-sg * mil[e], ui, mrl[e] * ur)));
+      xi = fma_(sg * mi[e], ur, fma_(mr[e], ui, fma_(sg * mil[e], ur, mrl[e] * ui)));
     } else {
       xr = mr[e] * ur - sg * mi[e] * ui;
       xi = mr[e] * ui + sg * mi[e] * ur;
@@ -173,8 +190,8 @@ __device__ __forceinline__ void apply_lane_digits(const Lane<T, Q, L, LD> &ln, c
     for (int e = 0; e < G::EPL; ++e) {
       const T ur = lane_shift<T, L, ST, true>(vr[e], ln.up[JJ]), ui = lane_shift<T, L, ST, true>(vi[e], ln.up[JJ]);
       const T dr_ = lane_shift<T, L, ST, false>(vr[e], ln.dn[JJ]), di_ = lane_shift<T, L, ST, false>(vi[e], ln.dn[JJ]);
-      Sr[e] += lor[JJ] * ur - loi[JJ] * ui + hir[JJ] * dr_ - hii[JJ] * di_;
-      Si[e] += lor[JJ] * ui + loi[JJ] * ur + hir[JJ] * di_ + hii[JJ] * dr_;
+      cmac(Sr[e], Si[e], lor[JJ], loi[JJ], ur, ui);
+      cmac(Sr[e], Si[e], hir[JJ], hii[JJ], dr_, di_);
     }
     apply_lane_digits<T, Q, L, LD, JJ + 1>(ln, lor, loi, hir, hii, vr, vi, Sr, Si);
   }
@@ -195,13 +212,11 @@ __device__ __forceinline__ void apply_Hc(const Lane<T, Q, L, LD> &ln, const T *c
       const int st = G::rstride(j);
       if (l < L - 1) {  // c'_j sqrt(l+1) v[e+st]
         const T ar = cr[j] * (T)sqrt((double)(l + 1)), ai = ci[j] * (T)sqrt((double)(l + 1));
-        Sr[e] += ar * vr[e + st] - ai * vi[e + st];
-        Si[e] += ar * vi[e + st] + ai * vr[e + st];
+        cmac(Sr[e], Si[e], ar, ai, vr[e + st], vi[e + st]);
       }
       if (l > 0) {      // conj(c'_j) sqrt(l) v[e-st]
         const T ar = cr[j] * (T)sqrt((double)l), ai = ci[j] * (T)sqrt((double)l);
-        Sr[e] += ar * vr[e - st] + ai * vi[e - st];
-        Si[e] += ar * vi[e - st] - ai * vr[e - st];
+        cmac_conj(Sr[e], Si[e], ar, ai, vr[e - st], vi[e - st]);
       }
     }
   }
@@ -261,11 +276,11 @@ __device__ __forceinline__ void solve_increment(const Lane<T, Q, L, LD> &ln, int
 #pragma unroll
     for (int e = 0; e < G::EPL; ++e) {
       if (!REV) {   // w = x - i D^{-1} S
-        wr[e] = xr[e] + ln.dr[e] * Si[e] + ln.di[e] * Sr[e];
-        wi[e] = xi[e] - ln.dr[e] * Sr[e] + ln.di[e] * Si[e];
+        wr[e] = fma_(ln.dr[e], Si[e], fma_(ln.di[e], Sr[e], xr[e]));
+        wi[e] = fma_(-ln.dr[e], Sr[e], fma_(ln.di[e], Si[e], xi[e]));
       } else {      // w = x + i conj(D)^{-1} S
-        wr[e] = xr[e] - ln.dr[e] * Si[e] + ln.di[e] * Sr[e];
-        wi[e] = xi[e] + ln.dr[e] * Sr[e] + ln.di[e] * Si[e];
+        wr[e] = fma_(-ln.dr[e], Si[e], fma_(ln.di[e], Sr[e], xr[e]));
+        wi[e] = fma_(ln.dr[e], Sr[e], fma_(ln.di[e], Si[e], xi[e]));
       }
     }
   }
@@ -279,12 +294,8 @@ __device__ __forceinline__ void solve_increment(const Lane<T, Q, L, LD> &ln, int
 // checkpoints U_{k0 + i*C} are written on the way.  ROLLOUT: a single window over
 // all steps from W^0, writing the states at the window boundaries instead.
 template <typename T, int Q, int L, int LD, bool ROLLOUT>
-__global__ __launch_bounds__(64) void k_forward(DevSys s, double *Wout, double *Uout, int nitems) {
+__device__ __forceinline__ void forward_item(const DevSys &s, int m, int cg, double *Wout, double *Uout) {
   using G = Geo<T, Q, L, LD>;
-  const int item = xcd_item(blockIdx.x, gridDim.x);
-  if (item >= nitems) return;
-  const int m = ROLLOUT ? 0 : item / s.ncg;      // 0-based window
-  const int cg = ROLLOUT ? item : item % s.ncg;
   Lane<T, Q, L, LD> ln;
   ln.init(s, cg);
 
@@ -349,6 +360,14 @@ __global__ __launch_bounds__(64) void k_forward(DevSys s, double *Wout, double *
   for (int e = 0; e < G::EPL; ++e) dst[ln.row(e)] = double2{udr[e], udi[e]};
 }
 
+template <typename T, int Q, int L, int LD, bool ROLLOUT>
+__global__ __launch_bounds__(64) void k_forward(DevSys s, double *Wout, double *Uout, int nitems) {
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  if (item >= nitems) return;
+  if (ROLLOUT) forward_item<T, Q, L, LD, true>(s, 0, item, Wout, Uout);
+  else forward_item<T, Q, L, LD, false>(s, item / s.ncg, item % s.ncg, nullptr, nullptr);
+}
+
 // Lane-digit part of the per-step inner products.
 template <typename T, int Q, int L, int LD, int JJ = 0>
 __device__ __forceinline__ void inner_lane_digits(const Lane<T, Q, L, LD> &ln, const T *zr, const T *zi, const T *yr,
@@ -361,8 +380,8 @@ __device__ __forceinline__ void inner_lane_digits(const Lane<T, Q, L, LD> &ln, c
     for (int e = 0; e < G::EPL; ++e) {
       const T zur = lane_shift<T, L, ST, true>(zr[e], ln.up[JJ]), zui = lane_shift<T, L, ST, true>(zi[e], ln.up[JJ]);
       const T yur = lane_shift<T, L, ST, true>(yr[e], ln.up[JJ]), yui = lane_shift<T, L, ST, true>(yi[e], ln.up[JJ]);
-      a1 += yr[e] * zui - yi[e] * zur + yur * zi[e] - yui * zr[e];
-      a2 += yr[e] * zur + yi[e] * zui - yur * zr[e] - yui * zi[e];
+      a1 = fma_(yr[e], zui, a1); a1 = fma_(-yi[e], zur, a1); a1 = fma_(yur, zi[e], a1); a1 = fma_(-yui, zr[e], a1);
+      a2 = fma_(yr[e], zur, a2); a2 = fma_(yi[e], zui, a2); a2 = fma_(-yur, zr[e], a2); a2 = fma_(-yui, zi[e], a2);
     }
     s1[G::R + JJ] = ln.wlo[JJ] * a1;
     s2[G::R + JJ] = ln.wlo[JJ] * a2;
@@ -372,12 +391,19 @@ __device__ __forceinline__ void inner_lane_digits(const Lane<T, Q, L, LD> &ln, c
 
 // ---------------------------------------------------------------------------- backward sweep
 
-// FP64 sum over the wavefront; every lane receives the total.
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
+// Per-step inner products are reduced over the wavefront's 64 lanes through LDS:
+// every step each lane stores its 2q partial sums (propagation precision); every RB steps
+// lane i sums, in FP64 and in lane order, the 64 partials of one (step, value)
+// pair and writes it to the series (one coalesced store per flush).
+constexpr int kRedFloats = 36 * 64;             // LDS elements per wavefront (all q)
+
+template <int Q>
+struct SeriesBuf {
+  static constexpr int NV = 2 * Q;               // values per step
+  static constexpr int RS = 64 * NV + 8;         // elements per buffered step (padded)
+  static constexpr int RB = (kRedFloats / RS < 64 / NV) ? kRedFloats / RS : 64 / NV;   // steps per flush
+  static_assert(RB >= 1, "reduction buffer too small");
+};
 
 // One wavefront per (window, column group).  Starting from U^m(t_m) and the
 // terminal condition of eq. terminal, each step k (descending) solves
@@ -394,12 +420,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 // propagated, and the W-gradient adds the dropped part back exactly:
 // Lambda^M(t_{M-1}) = -W^{M-1}/E + (propagated part)  (App. B, eq. back-prop-2).
 template <typename T, int Q, int L, int LD>
-__global__ __launch_bounds__(64) void k_backward(DevSys s, int nitems) {
+__device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T *red) {
   using G = Geo<T, Q, L, LD>;
-  const int item = xcd_item(blockIdx.x, gridDim.x);
-  if (item >= nitems) return;
-  const int m = item / s.ncg;
-  const int cg = item % s.ncg;
+  const int item = m * s.ncg + cg;
   Lane<T, Q, L, LD> ln;
   ln.init(s, cg);
 
@@ -467,22 +490,36 @@ __global__ __launch_bounds__(64) void k_backward(DevSys s, int nitems) {
         if (l < L - 1) {
           const int f = e + G::rstride(j);
           const T w = (T)sqrt((double)(l + 1));
-          s1[j] += w * (yr[e] * zi[f] - yi[e] * zr[f] + yr[f] * zi[e] - yi[f] * zr[e]);
-          s2[j] += w * (yr[e] * zr[f] + yi[e] * zi[f] - yr[f] * zr[e] - yi[f] * zi[e]);
+          T a1 = yr[e] * zi[f], a2 = yr[e] * zr[f];
+          a1 = fma_(-yi[e], zr[f], a1); a1 = fma_(yr[f], zi[e], a1); a1 = fma_(-yi[f], zr[e], a1);
+          a2 = fma_(yi[e], zi[f], a2); a2 = fma_(-yr[f], zr[e], a2); a2 = fma_(-yi[f], zi[e], a2);
+          s1[j] = fma_(w, a1, s1[j]);
+          s2[j] = fma_(w, a2, s2[j]);
         }
       }
     }
     inner_lane_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
-    double v[2 * Q];
+    {
+      using SB = SeriesBuf<Q>;
+      const int idx = (int)(k - k0);
+      T *slot = red + (idx % SB::RB) * SB::RS + ln.lane * SB::NV;
 #pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      v[2 * j] = wave_sum((double)s1[j]);
-      v[2 * j + 1] = wave_sum((double)s2[j]);
-    }
-    if (ln.lane == 0) {
-      double *dst = ser + (size_t)(k - k0) * 2 * Q;
-#pragma unroll
-      for (int i = 0; i < 2 * Q; ++i) dst[i] = v[i];
+      for (int j = 0; j < Q; ++j) {
+        slot[2 * j] = s1[j];
+        slot[2 * j + 1] = s2[j];
+      }
+      if (idx % SB::RB == 0) {             // steps idx .. idx+RB-1 are buffered: flush
+        __syncthreads();
+        const int r = ln.lane / SB::NV, vv = ln.lane % SB::NV;
+        if (r < SB::RB && idx + r < (int)(k1 - k0)) {
+          const T *col = red + r * SB::RS + vv;
+          double acc = 0.0;
+#pragma unroll 8
+          for (int l = 0; l < 64; ++l) acc += (double)col[l * SB::NV];
+          ser[(size_t)(idx + r) * SB::NV + vv] = acc;
+        }
+        __syncthreads();
+      }
     }
 #pragma unroll
     for (int e = 0; e < G::EPL; ++e) {
@@ -509,6 +546,14 @@ __global__ __launch_bounds__(64) void k_backward(DevSys s, int nitems) {
   for (int e = 0; e < G::EPL; ++e) l0[ln.row(e)] = double2{ldr[e], ldi[e]};
 }
 
+template <typename T, int Q, int L, int LD>
+__global__ __launch_bounds__(64) void k_backward(DevSys s, int nitems) {
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  if (item >= nitems) return;
+  __shared__ T red[kRedFloats];
+  backward_item<T, Q, L, LD>(s, item / s.ncg, item % s.ncg, red);
+}
+
 // ---------------------------------------------------------------------------- small FP64 kernels
 
 // Fixed-point iteration count.  The Jacobi map w -> (D^{-1} - 1)u - i D^{-1} (dt/2) H_c (u + w)
@@ -516,7 +561,7 @@ __global__ __launch_bounds__(64) void k_backward(DevSys s, int nitems) {
 // c'_j = (dt/2) 2 pi d_j and nu_L = ||a + a^+||_2; k_controls leaves max_k of that bound
 // in rho_bits.  Starting from w = (D^{-1} - 1)u, K iterations leave an error
 // <= rho^(K+1) |z|; K is the smallest count with rho^(K+1) <= solve_tol.
-__global__ void k_kit(DevSys s) {
+__device__ void kit_block(const DevSys &s) {
   if (threadIdx.x != 0) return;
   const double rho = (double)__uint_as_float(*s.rho_bits) * (1.0 + 1e-6);
   *s.rho_bits = 0u;                  // reset for the next evaluation
@@ -530,10 +575,10 @@ __global__ void k_kit(DevSys s) {
 // (dt/2) * 2 pi d_j(t_{k+1/2}) for every step; B_s(t) = B(t/dtau + 1/2 - s); and the
 // per-step contraction bound nu_L sum_j |c'_j| maximised into rho_bits.
 template <typename T>
-__global__ __launch_bounds__(256) void k_controls(DevSys s) {
+__device__ void controls_block(const DevSys &s, int blk) {
   using V2 = typename C2<T>::type;
   __shared__ float smax[256];
-  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long k = (long long)blk * 256 + threadIdx.x;
   float rho = 0.f;
   if (k < s.NT) {
     const double t = (k + 0.5) * s.dt;
@@ -587,9 +632,8 @@ __device__ double block_sum(double v, double *sh) {
 }
 
 // Per window: |U^m - W^m|_F^2 (m < M) or |U^M|_F^2 and gamma = <V, U^M>_F (m = M), in FP64.
-__global__ __launch_bounds__(256) void k_boundary_partial(DevSys s) {
+__device__ void boundary_partial_block(const DevSys &s, int m) {
   __shared__ double sh[256];
-  const int m = blockIdx.x;
   const size_t n = (size_t)s.E * s.N;
   const double2 *u = reinterpret_cast<const double2 *>(s.Ufin) + (size_t)m * n;
   double a = 0.0, b = 0.0, c = 0.0;
@@ -618,7 +662,7 @@ __global__ __launch_bounds__(256) void k_boundary_partial(DevSys s) {
   }
 }
 
-__global__ void k_boundary_final(DevSys s) {
+__device__ void boundary_final_block(const DevSys &s) {
   if (threadIdx.x != 0) return;
   double pen = 0.0;
   for (int m = 0; m < s.M - 1; ++m) {
@@ -638,8 +682,8 @@ __global__ void k_boundary_final(DevSys s) {
 }
 
 // xy[k] = sum over the window's column groups of the per-wavefront series.
-__global__ void k_series_reduce(DevSys s) {
-  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void series_reduce_block(const DevSys &s, int blk) {
+  const long long k = (long long)blk * 256 + threadIdx.x;
   if (k >= s.NT) return;
   const int m = (int)(((k + 1) * s.M - 1) / s.NT);   // window of step k under the floor split
   const long long kk = k - s.kstart[m];
@@ -655,9 +699,8 @@ __global__ void k_series_reduce(DevSys s) {
 // Y = -2 dt 2 pi Re<y,(a-a^+)z> per step,
 //   dP/dalpha1 = sum_k B_s(t_k) (cos(W t_k) X_k + sin(W t_k) Y_k),
 //   dP/dalpha2 = sum_k B_s(t_k) (-sin(W t_k) X_k + cos(W t_k) Y_k).
-__global__ __launch_bounds__(256) void k_project(DevSys s) {
+__device__ void project_block(const DevSys &s, int b) {
   __shared__ double sh[256];
-  const int b = blockIdx.x;
   const int sp = b % s.d1, jf = b / s.d1, j = jf / s.nf;
   const double om = s.carrier[jf];
   const double r = s.dtau / s.dt;
@@ -686,9 +729,9 @@ __global__ __launch_bounds__(256) void k_project(DevSys s) {
 // dP/dW^m = mu (W^m - U^m(t_m)) - 2 Lambda^{m+1}(t_m).  For m = M-1 the backward sweep
 // propagated only gamma V/E^2 of the last window's terminal condition; the dropped part
 // -U^M/E equals -W^{M-1}/E at t_{M-1}, which adds (2/E) W^{M-1} here.
-__global__ void k_grad_W(DevSys s) {
+__device__ void grad_W_block(const DevSys &s, int blk) {
   const size_t n = (size_t)s.E * s.N;
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t idx = (size_t)blk * 256 + threadIdx.x;
   if (idx >= (size_t)(s.M - 1) * n) return;
   const size_t m = idx / n, rest = idx % n;       // window m+1 (1-based) ends at t_{m+1}
   const double2 u = reinterpret_cast<const double2 *>(s.Ufin)[m * n + rest];
@@ -697,6 +740,29 @@ __global__ void k_grad_W(DevSys s) {
   const double extra = (m + 2 == (size_t)s.M) ? 2.0 / (double)s.E : 0.0;
   s.grad_W[2 * idx] = s.mu * (w.x - u.x) - 2.0 * l.x + extra * w.x;
   s.grad_W[2 * idx + 1] = s.mu * (w.y - u.y) - 2.0 * l.y + extra * w.y;
+}
+
+// Single-system kernels and their batched forms.  A batched launch reads, per
+// block, (system index, block index within that system) from a table.
+template <typename T, int K>
+__device__ __forceinline__ void small_block(const DevSys &s, int blk) {
+  if constexpr (K == SK_CONTROLS) controls_block<T>(s, blk);
+  else if constexpr (K == SK_KIT) kit_block(s);
+  else if constexpr (K == SK_BPARTIAL) boundary_partial_block(s, blk);
+  else if constexpr (K == SK_BFINAL) boundary_final_block(s);
+  else if constexpr (K == SK_SERIES) series_reduce_block(s, blk);
+  else if constexpr (K == SK_PROJECT) project_block(s, blk);
+  else grad_W_block(s, blk);
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_small(DevSys s) { small_block<T, K>(s, blockIdx.x); }
+
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_small_batch(const DevSys *sys, const int2 *blocks) {
+  const int2 b = blocks[blockIdx.x];
+  const DevSys s = sys[b.x];
+  small_block<T, K>(s, b.y);
 }
 
 // ---------------------------------------------------------------------------- dispatch
@@ -713,7 +779,7 @@ Kernels make() {
 }
 
 // (q, L) -> lane digits, chosen so that each lane holds at most four entries
-// per state (the backward sweep keeps 16 such arrays live).
+// per state (the backward sweep keeps about 16 such arrays live).
 #define QOC_SHAPES(X)   \
   X(1, 2, 0) X(1, 3, 0) X(1, 4, 0) \
   X(2, 2, 0) X(2, 3, 1) X(2, 4, 1) \
@@ -721,13 +787,18 @@ Kernels make() {
   X(4, 2, 2) X(4, 3, 3) X(4, 4, 3) \
   X(5, 2, 3) X(6, 2, 4)
 
+#define X(Q_, L_, LD_) SHAPE_##Q_##_##L_,
+enum ShapeId { QOC_SHAPES(X) N_SHAPES };
+#undef X
+
 template <typename T>
-bool lookup(int q, int L, Kernels *k, int *ld, int *cpw) {
+bool lookup(int q, int L, Kernels *k, int *ld, int *cpw, int *shape) {
 #define X(Q_, L_, LD_)                                                 \
   if (q == Q_ && L == L_) {                                            \
     if (k) *k = make<T, Q_, L_, LD_>();                                \
     *ld = LD_;                                                         \
     *cpw = Geo<T, Q_, L_, LD_>::CPW;                                   \
+    if (shape) *shape = SHAPE_##Q_##_##L_;                             \
     return true;                                                       \
   }
   QOC_SHAPES(X)
@@ -735,38 +806,70 @@ bool lookup(int q, int L, Kernels *k, int *ld, int *cpw) {
   return false;
 }
 
+// Batched propagation: one wavefront per item (system, window, column group, shape),
+// items ordered by the host (longest first).
+template <typename T>
+__global__ __launch_bounds__(64) void k_forward_batch(const DevSys *sys, const int4 *items) {
+  const int4 it = items[blockIdx.x];
+  const DevSys s = sys[it.x];
+  switch (it.w) {
+#define X(Q_, L_, LD_) \
+    case SHAPE_##Q_##_##L_: forward_item<T, Q_, L_, LD_, false>(s, it.y, it.z, nullptr, nullptr); break;
+    QOC_SHAPES(X)
+#undef X
+    default: break;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_backward_batch(const DevSys *sys, const int4 *items) {
+  __shared__ T red[kRedFloats];
+  const int4 it = items[blockIdx.x];
+  const DevSys s = sys[it.x];
+  switch (it.w) {
+#define X(Q_, L_, LD_) \
+    case SHAPE_##Q_##_##L_: backward_item<T, Q_, L_, LD_>(s, it.y, it.z, red); break;
+    QOC_SHAPES(X)
+#undef X
+    default: break;
+  }
+}
+
 int grid8(int n) { return (n + 7) / 8 * 8; }
+
+template <typename T, int K>
+void small(const DevSys &s, hipStream_t st) {
+  const int nb = small_blocks(s, K);
+  if (nb > 0) hipLaunchKernelGGL((k_small<T, K>), dim3(nb), dim3(256), 0, st, s);
+}
 
 template <typename T>
 int phase_T(const DevSys &s, int phase, hipStream_t st, double *Wout, double *Ufinal) {
   Kernels K;
   int ld, cpw;
-  if (!lookup<T>(s.q, s.L, &K, &ld, &cpw)) return (int)hipErrorInvalidValue;
+  if (!lookup<T>(s.q, s.L, &K, &ld, &cpw, nullptr)) return (int)hipErrorInvalidValue;
   const int nitems = s.M * s.ncg;
   switch (phase) {
     case PHASE_CONTROLS:
-      hipLaunchKernelGGL(k_controls<T>, dim3((unsigned)((s.NT + 255) / 256)), dim3(256), 0, st, s);
-      hipLaunchKernelGGL(k_kit, dim3(1), dim3(64), 0, st, s);
+      small<T, SK_CONTROLS>(s, st);
+      small<T, SK_KIT>(s, st);
       break;
     case PHASE_FORWARD:
       hipLaunchKernelGGL(K.fwd, dim3(grid8(nitems)), dim3(64), 0, st, s, (double *)nullptr, (double *)nullptr, nitems);
       break;
     case PHASE_BOUNDARY:
-      hipLaunchKernelGGL(k_boundary_partial, dim3(s.M), dim3(256), 0, st, s);
-      hipLaunchKernelGGL(k_boundary_final, dim3(1), dim3(64), 0, st, s);
+      small<T, SK_BPARTIAL>(s, st);
+      small<T, SK_BFINAL>(s, st);
       break;
     case PHASE_BACKWARD:
       hipLaunchKernelGGL(K.bwd, dim3(grid8(nitems)), dim3(64), 0, st, s, nitems);
       break;
     case PHASE_PROJECT:
-      hipLaunchKernelGGL(k_series_reduce, dim3((unsigned)((s.NT + 255) / 256)), dim3(256), 0, st, s);
-      hipLaunchKernelGGL(k_project, dim3(s.q * s.nf * s.d1), dim3(256), 0, st, s);
+      small<T, SK_SERIES>(s, st);
+      small<T, SK_PROJECT>(s, st);
       break;
     case PHASE_GRAD_W:
-      if (s.M > 1) {
-        const size_t n = (size_t)(s.M - 1) * s.E * s.N;
-        hipLaunchKernelGGL(k_grad_W, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s);
-      }
+      small<T, SK_GRADW>(s, st);
       break;
     case PHASE_ROLLOUT:
       hipLaunchKernelGGL(K.roll, dim3(grid8(s.ncg)), dim3(64), 0, st, s, Wout, Ufinal, s.ncg);
@@ -777,14 +880,67 @@ int phase_T(const DevSys &s, int phase, hipStream_t st, double *Wout, double *Uf
   return (int)hipGetLastError();
 }
 
+template <typename T, int K>
+void small_batched(const BatchPlan &p, hipStream_t st) {
+  if (p.n_blocks[K] > 0)
+    hipLaunchKernelGGL((k_small_batch<T, K>), dim3(p.n_blocks[K]), dim3(256), 0, st, p.sys, p.blocks[K]);
+}
+
+template <typename T>
+int batch_phase_T(const BatchPlan &p, int phase, hipStream_t st) {
+  switch (phase) {
+    case PHASE_CONTROLS:
+      small_batched<T, SK_CONTROLS>(p, st);
+      small_batched<T, SK_KIT>(p, st);
+      break;
+    case PHASE_FORWARD:
+      if (p.n_fwd > 0) hipLaunchKernelGGL(k_forward_batch<T>, dim3(p.n_fwd), dim3(64), 0, st, p.sys, p.fwd_items);
+      break;
+    case PHASE_BOUNDARY:
+      small_batched<T, SK_BPARTIAL>(p, st);
+      small_batched<T, SK_BFINAL>(p, st);
+      break;
+    case PHASE_BACKWARD:
+      if (p.n_bwd > 0) hipLaunchKernelGGL(k_backward_batch<T>, dim3(p.n_bwd), dim3(64), 0, st, p.sys, p.bwd_items);
+      break;
+    case PHASE_PROJECT:
+      small_batched<T, SK_SERIES>(p, st);
+      small_batched<T, SK_PROJECT>(p, st);
+      break;
+    case PHASE_GRAD_W:
+      small_batched<T, SK_GRADW>(p, st);
+      break;
+    default:
+      return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
+
 }  // namespace
 
-bool layout_for(int q, int L, int fp64, int *ld, int *cpw) {
-  return fp64 ? lookup<double>(q, L, nullptr, ld, cpw) : lookup<float>(q, L, nullptr, ld, cpw);
+int small_blocks(const DevSys &s, int kind) {
+  switch (kind) {
+    case SK_CONTROLS: return (int)((s.NT + 255) / 256);
+    case SK_KIT: return 1;
+    case SK_BPARTIAL: return s.M;
+    case SK_BFINAL: return 1;
+    case SK_SERIES: return (int)((s.NT + 255) / 256);
+    case SK_PROJECT: return s.q * s.nf * s.d1;
+    case SK_GRADW: return s.M > 1 ? (int)(((size_t)(s.M - 1) * s.E * s.N + 255) / 256) : 0;
+    default: return 0;
+  }
+}
+
+bool layout_for(int q, int L, int fp64, int *ld, int *cpw, int *shape) {
+  return fp64 ? lookup<double>(q, L, nullptr, ld, cpw, shape) : lookup<float>(q, L, nullptr, ld, cpw, shape);
 }
 
 int launch_phase(const DevSys &s, int phase, hipStream_t st, double *Wout, double *Ufinal) {
   return s.fp64 ? phase_T<double>(s, phase, st, Wout, Ufinal) : phase_T<float>(s, phase, st, Wout, Ufinal);
+}
+
+int launch_batch_phase(const BatchPlan &p, int phase, hipStream_t st) {
+  return p.fp64 ? batch_phase_T<double>(p, phase, st) : batch_phase_T<float>(p, phase, st);
 }
 
 }  // namespace qoc

@@ -30,7 +30,8 @@ QOC_FP64, QOC_FP32 = 0, 1
 
 EXPORTED = ["qoc_create", "qoc_destroy", "qoc_get_info", "qoc_set_stream", "qoc_set_controls",
             "qoc_set_window_states", "qoc_objective", "qoc_gradient", "qoc_rollout", "qoc_synchronize",
-            "qoc_last_error", "qoc_strerror", "qoc_enable_timing", "qoc_get_timings", "qoc_backward"]
+            "qoc_last_error", "qoc_strerror", "qoc_enable_timing", "qoc_get_timings", "qoc_backward",
+            "qoc_batch_create", "qoc_batch_destroy", "qoc_batch_run", "qoc_read_results"]
 
 PHASES = ["controls", "forward", "boundary", "backward", "project", "grad_W", "total"]
 
@@ -87,6 +88,10 @@ def load_library(path: str = LIB_PATH):
         "qoc_gradient": ([vp, vp, vp, vp, vp, i32], ctypes.c_int),
         "qoc_rollout": ([vp, vp, vp, i32], ctypes.c_int),
         "qoc_backward": ([vp, vp, vp, i32], ctypes.c_int),
+        "qoc_batch_create": ([i32, i32, i64, ctypes.POINTER(vp)], ctypes.c_int),
+        "qoc_batch_destroy": ([vp], ctypes.c_int),
+        "qoc_batch_run": ([vp, ctypes.POINTER(vp), i32, vp, vp], ctypes.c_int),
+        "qoc_read_results": ([vp, vp, vp, vp, vp, i32], ctypes.c_int),
         "qoc_synchronize": ([vp], ctypes.c_int),
         "qoc_last_error": ([], ctypes.c_char_p),
         "qoc_strerror": ([ctypes.c_int], ctypes.c_char_p),
@@ -257,6 +262,18 @@ class System:
     def synchronize(self):
         _check(_lib.qoc_synchronize(self.h))
 
+    def read_results(self, device: bool = False, grad: bool = True):
+        """(P, terms, grad_alpha, grad_W) of the last evaluation (e.g. a batched one)."""
+        out, ptr = self._outputs(device, grad=grad)
+        _check(_lib.qoc_read_results(self.h, ptr["P"], ptr["terms"], ptr.get("grad_alpha"), ptr.get("grad_W"),
+                                     QOC_DEVICE if device else QOC_HOST))
+        P = out["P"] if device else float(out["P"][0])
+        return P, out["terms"], out.get("grad_alpha"), out.get("grad_W")
+
+    def read_results_into(self, P, terms, grad_alpha, grad_W):
+        ptr = lambda t: t.data_ptr() if t is not None else None
+        _check(_lib.qoc_read_results(self.h, ptr(P), ptr(terms), ptr(grad_alpha), ptr(grad_W), QOC_DEVICE))
+
     def enable_timing(self, on: bool = True):
         _check(_lib.qoc_enable_timing(self.h, 1 if on else 0))
 
@@ -267,3 +284,37 @@ class System:
         out = {name: t.mean_ms[i] for i, name in enumerate(PHASES)}
         out.update(n_calls=t.n_calls, n_grad_calls=t.n_grad_calls, fixed_point_iters=t.fixed_point_iters)
         return out
+
+
+class Batch:
+    """Batched evaluation of several Systems: one launch per phase for all of them (qoc_batch_*)."""
+
+    def __init__(self, max_contexts: int, max_items: int, device: int = 0):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.qoc_batch_create(device, max_contexts, max_items, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            _lib.qoc_batch_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, systems, want_grad=None, stream: Optional[int] = None):
+        """Evaluate all systems (their current inputs) asynchronously on `stream` (default: torch's current)."""
+        n = len(systems)
+        arr = (ctypes.c_void_p * n)(*[s.h.value for s in systems])
+        wg = None
+        if want_grad is not None:
+            self._wg = (ctypes.c_int32 * n)(*[1 if g else 0 for g in want_grad])
+            wg = ctypes.cast(self._wg, ctypes.c_void_p)
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        _check(_lib.qoc_batch_run(self.h, arr, n, wg, ctypes.c_void_p(stream)))
