@@ -43,6 +43,22 @@ def algorithmic_flops(w, kit):
     return fwd * units, bwd * units
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE runs,
+    or None when the kernel source has changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_k_backward_q4L4.json")
+    src = os.path.join(ROOT, "paper_2407_13950_amd", "csrc", "qoc_kernels.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("source_sha256") != sha or rec.get("kernel") != kernel:
+        return None
+    return rec["bytes_per_launch"]
+
+
 def percentile(xs, p):
     xs = sorted(xs)
     if not xs:
@@ -127,7 +143,7 @@ def bench_serve(rate, n_requests, plain_requests, seed, budget_gb, log):
     out = {"rate_rps": rate, "requests": n_requests, "runs": 64, "objective_only": 0.1,
            "hbm_budget_GB": budget_gb}
     runs, reqs, counts = serve.make_trace(n_requests, rate=rate, seed=seed, n_runs=64)
-    be = serve.QocBackend(precision="fp32", n_streams=2, max_batch=64, max_items=400000)
+    be = serve.QocBackend(precision="fp32", n_streams=4, max_batch=64, max_items=400000)
     srv = serve.Server(be, hbm_budget=int(budget_gb * (1 << 30)), max_batch=64)
     for r, w in runs.items():
         srv.register_run(r, w, counts[r], initial=serve.initial_inputs(w, 1000 + r))
@@ -233,6 +249,8 @@ def main():
     dominant = "backward" if tm["backward"] >= tm["forward"] else "forward"
     flops = f_bwd if dominant == "backward" else f_fwd
     achieved = flops / (tm[dominant] * 1e-3) / 1e12
+    tname = "float" if args.precision == "fp32" else "double"
+    kname = f"k_backward<{tname}, 4, 4, 3>" if dominant == "backward" else f"k_forward<{tname}, 4, 4, 3, false>"
     value = args.steps / elapsed
     result = {
         "metric": "objective+gradient evals/s at 4 qubits",
@@ -254,13 +272,12 @@ def main():
         "window_steps_per_s": value * 2 * w.n_steps,
         "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
         "phases_ms": {k: tm[k] for k in qoc.PHASES},
-        "roofline": {"kernel": f"k_backward<{'float' if args.precision == 'fp32' else 'double'},4,4,3>"
-                     if dominant == "backward" else "k_forward",
+        "roofline": {"kernel": kname,
                      "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP32_VECTOR_TFLOPS if args.precision == "fp32" else PEAK_FP64_VECTOR_TFLOPS,
                      "unit": "TFLOP/s",
                      "frac": achieved / (PEAK_FP32_VECTOR_TFLOPS if args.precision == "fp32" else PEAK_FP64_VECTOR_TFLOPS),
-                     "traffic": None,
+                     "traffic": measured_traffic(kname),
                      "peak_without_packed_fp32": PEAK_FP32_NONPACKED_TFLOPS,
                      "flops_per_launch": flops, "mean_launch_ms": tm[dominant]},
         "P": float(P.item()),

@@ -92,10 +92,16 @@ __device__ __forceinline__ double bspline2(double x) {
 // Lane shift for lane digit jj: DPP row shift when every shifted pair stays in
 // one 16-lane row (L a power of two and the digit block L^(k+1) <= 16), else a
 // cross-lane permute through the LDS crossbar.
+// QOC_DPP_BLOCK: largest digit block (L^(k+1)) shifted with DPP; 16 = every in-row
+// shift, 4 = only the innermost digit, 1 = none (all through the LDS crossbar, which
+// keeps the VALU free for the arithmetic).
+#ifndef QOC_DPP_BLOCK
+#define QOC_DPP_BLOCK 16
+#endif
 template <int L, int ST>
 struct ShiftKind {
   static constexpr bool pow2 = (L & (L - 1)) == 0;
-  static constexpr bool dpp = pow2 && ST * L <= 16;
+  static constexpr bool dpp = pow2 && ST * L <= 16 && ST * L <= QOC_DPP_BLOCK;
 };
 
 template <int CTRL>
@@ -688,11 +694,18 @@ __device__ void series_reduce_block(const DevSys &s, int blk) {
   const int m = (int)(((k + 1) * s.M - 1) / s.NT);   // window of step k under the floor split
   const long long kk = k - s.kstart[m];
   const int w = 2 * s.q;
-  for (int i = 0; i < w; ++i) {
-    double acc = 0.0;
-    for (int cg = 0; cg < s.ncg; ++cg) acc += s.series[(((size_t)m * s.ncg + cg) * s.maxlen + kk) * w + i];
-    s.xy[(size_t)k * w + i] = acc;
+  double acc[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) acc[i] = 0.0;
+  for (int cg = 0; cg < s.ncg; ++cg) {       // one contiguous record of 2q values per column group
+    const double *src = s.series + (((size_t)m * s.ncg + cg) * s.maxlen + kk) * w;
+#pragma unroll
+    for (int i = 0; i < 12; ++i)
+      if (i < w) acc[i] += src[i];
   }
+#pragma unroll
+  for (int i = 0; i < 12; ++i)
+    if (i < w) s.xy[(size_t)k * w + i] = acc[i];
 }
 
 // dP/dalpha for one (qubit j, carrier f, spline s): with X = -2 dt 2 pi Im<y,(a+a^+)z>,

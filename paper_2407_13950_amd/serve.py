@@ -10,7 +10,10 @@ evaluation and whether the gradient is wanted.  The scheduler
   * serialises the requests of one run (its device buffers are reused),
   * launches a batch on any idle stream as soon as there is admitted work --
     requests that arrive while other batches are on the GPU go into the next
-    batch, so batches overlap on the device -- and
+    batch, so batches overlap on the device; a batch takes the oldest ready
+    request and then only requests of the same duration class (a batch
+    completes as a whole, so a short request must not wait for a long window
+    chain) -- and
   * retires a batch when its completion event has passed, stamping each
     request's completion time (latency = completion - arrival).
 
@@ -58,12 +61,16 @@ class Run:
     busy: bool = False
     remaining: int = 0                   # requests still to arrive or complete
     admitted: bool = False
+    cls: int = 0                         # duration class of one evaluation
 
 
 class Backend:
     """Device operations the scheduler needs (the HIP implementation is QocBackend)."""
 
     def footprint(self, workload) -> int: ...
+    def duration_class(self, workload) -> int:
+        """Requests of one class are batched together (0 = no distinction)."""
+        return 0
     def open(self, workload, initial) -> Any: ...
     def close(self, handle) -> None: ...
     def streams(self) -> int: ...
@@ -93,6 +100,7 @@ class Server:
         """initial: (alpha, W) the run starts from (device tensors or numpy)."""
         r = Run(run_id, workload, remaining=n_requests)
         r.footprint = self.backend.footprint(workload)
+        r.cls = self.backend.duration_class(workload)
         r.initial = initial
         self.runs[run_id] = r
         self.waiting_runs.append(run_id)
@@ -151,16 +159,23 @@ class Server:
         for st in range(self.backend.streams()):
             if st in self.inflight or not self.ready_runs:
                 continue
-            items, handles = [], []
-            while self.ready_runs and len(items) < self.max_batch:
-                r = self.runs[self.ready_runs.popleft()]
+            items, handles, rest, cls = [], [], collections.deque(), None
+            while self.ready_runs:
+                rid = self.ready_runs.popleft()
+                r = self.runs[rid]
                 if r.busy or not r.pending or not r.admitted:
+                    continue
+                if cls is None:
+                    cls = r.cls
+                if r.cls != cls or len(items) >= self.max_batch:
+                    rest.append(rid)
                     continue
                 req = r.pending.popleft()
                 r.busy = True
                 req.start = self.clock()
                 items.append(req)
                 handles.append(r.handle)
+            self.ready_runs = rest
             if items:
                 token = self.backend.launch(st, items, handles)
                 self.inflight[st] = (token, items, handles)
@@ -207,7 +222,7 @@ def summarize(done: List[Request], wall: float) -> Dict[str, float]:
 class QocBackend(Backend):
     """Runs batches through the C ABI: one qoc_batch per stream, one qoc context per run."""
 
-    def __init__(self, precision: str = "fp32", n_streams: int = 2, max_batch: int = 64, max_items: int = 400000,
+    def __init__(self, precision: str = "fp32", n_streams: int = 4, max_batch: int = 64, max_items: int = 400000,
                  keep_results: bool = False):
         import torch
         from . import qoc
@@ -220,6 +235,11 @@ class QocBackend(Backend):
 
     def streams(self) -> int:
         return len(self._streams)
+
+    def duration_class(self, w) -> int:
+        """log4 of the longest window's serial work (steps x qubits): one evaluation's critical path."""
+        longest = -(-w.n_steps // w.n_windows)
+        return int(math.log(max(longest * w.q, 1), 4))
 
     def footprint(self, w) -> int:
         key = (w.q, w.L, w.n_steps, w.n_windows, w.n_splines, w.n_carriers)

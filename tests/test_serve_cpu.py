@@ -128,3 +128,23 @@ def test_run_larger_than_budget_is_rejected():
     srv = serve.Server(be, hbm_budget=be.footprint(w) // 2, clock=clock)
     with pytest.raises(ValueError):
         srv.register_run(0, w, 3)
+
+
+class ClassedBackend(FakeBackend):
+    def duration_class(self, w):
+        return w.q
+
+
+def test_batches_hold_one_duration_class():
+    clock = FakeClock()
+    be = ClassedBackend(clock, n_streams=2)
+    runs = small_runs(15)
+    srv = serve.Server(be, hbm_budget=10 ** 12, max_batch=8, clock=clock)
+    _, reqs, counts = serve.make_trace(300, rate=20000.0, seed=6, n_runs=15)
+    for r, w in runs.items():
+        srv.register_run(r, w, counts[r])
+    srv.run_trace(reqs)
+    by_rid = {q.rid: q for q in srv.completed}
+    for st, rids in be.log:
+        assert len({runs[by_rid[i].run_id].q for i in rids}) == 1
+    assert len(srv.completed) == 300
