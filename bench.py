@@ -33,11 +33,13 @@ def log(msg):
 
 
 def algorithmic_flops(w, kit):
-    """Useful flops of one forward and one backward launch (measurement)."""
+    """Useful flops of one forward and one backward launch.  `kit` is the solve's count:
+    Jacobi iterations for odd L, red-black half sweeps (each refreshing half the entries) for even L."""
     q, L = w.q, w.L
     ladder = 16.0 * q * (L - 1) / L          # complex MACs of the nonzero ladder terms, per entry
     per_iter = ladder + 8.0                  # + z = x -/+ i D^-1 S
-    fwd = kit * per_iter + 10.0              # + D^-1 u and u' = 2z - u
+    sweeps = kit / 2.0 if L % 2 == 0 else float(kit)
+    fwd = sweeps * per_iter + 10.0           # + D^-1 u and u' = 2z - u
     bwd = 2.0 * fwd + ladder                 # two right-hand sides + the per-step inner products
     units = float(w.N) * w.E * w.n_steps     # entry-steps per sweep
     return fwd * units, bwd * units
@@ -186,7 +188,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is described in DESIGN.md but not built.", file=sys.stderr)
+              "multi-GPU sharding is not built.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

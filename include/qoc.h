@@ -85,7 +85,10 @@ typedef struct qoc_system_desc {
   double mu;                    /* penalty coefficient, >= 0                          */
   const double *target;         /* [2*E*E] unitary E x E target, column-major, host   */
   int32_t precision;            /* QOC_FP64 or QOC_FP32                               */
-  int32_t fixed_point_iters;    /* 0: derived per evaluation from a contraction bound */
+  int32_t fixed_point_iters;    /* 0: derived per evaluation from a contraction bound;
+                                   >0: forced count, no bound check.  Counts Jacobi
+                                   iterations for odd n_levels and red-black half
+                                   sweeps (half an iteration's work each) for even  */
   double solve_tol;             /* per-step fixed-point error target; 0: default      */
   int32_t checkpoint_every;     /* >0: store states every this many steps per window
                                    and re-sync the reverse reconstruction there; 0: none */
@@ -191,7 +194,8 @@ typedef struct qoc_timings {
   int32_t n_calls;              /* evaluations recorded                              */
   int32_t n_grad_calls;         /* of which gradient evaluations                     */
   double mean_ms[8];            /* mean kernel time per phase, ms                    */
-  int32_t fixed_point_iters;    /* iteration count used by the last evaluation       */
+  int32_t fixed_point_iters;    /* count used by the last evaluation (Jacobi
+                                   iterations, or half sweeps for even n_levels)     */
 } qoc_timings;
 int qoc_enable_timing(qoc_ctx *ctx, int32_t on);
 int qoc_get_timings(qoc_ctx *ctx, qoc_timings *out);

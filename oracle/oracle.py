@@ -8,7 +8,7 @@ only marshals numpy arrays (layouts as in the inputs module: window states
 
 Parity status: every function is pinned by tests/test_oracle_pins.py
 (closed forms, invariants, brute-force dense references, central finite
-differences); see the pin table in the design doc.
+differences).
 """
 from __future__ import annotations
 

@@ -9,7 +9,8 @@
  * seeded inputs.
  *
  * What is computed, in the paper's notation (n replaced by the number of
- * essential states E when guard levels are present):
+ * essential states E when guard levels are present: the target acts on the
+ * E essential rows and the guard rows of V are zero):
  *   model      H(t) = H_d + H_c(t), H_c = sum_j d_j a_j + conj(d_j) a_j^+  (Sec. 2, eqs. sys-ham, ctrl-ham)
  *              with the diagonal drift of the synthetic systems (detuning, anharmonicity, cross-Kerr).
  *   controls   d_j(t) = 2 pi sum_f exp(i Omega_jf t) sum_s (a1_jfs + i a2_jfs) B_s(t)   (Sec. 2, eq. dj-ctrl

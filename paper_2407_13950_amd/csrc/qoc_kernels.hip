@@ -27,6 +27,10 @@
 //
 // One fixed-point (Jacobi) iteration for (I + i dt/2 H) z = u with the diagonal
 // drift D = I + i dt/2 diag(h) split off:  z <- D^{-1} (u - i S), S = (dt/2) H_c z.
+// For even L the registers are instead arranged by colour (red-black slot layout,
+// see Geo): H_c only couples rows of opposite digit-sum parity, so the solve
+// refreshes one colour at a time from the other's newest values, which reaches the
+// Jacobi error bound of K iterations in K+1 half sweeps of half the work each.
 #include "qoc_internal.h"
 
 #include <cmath>
@@ -70,6 +74,16 @@ struct Geo {
   static constexpr int rstride(int j) { return cipow(L, R - 1 - j); }   // register digit j < R
   static constexpr int rdigit(int e, int j) { return (e / rstride(j)) % L; }
   static constexpr int lstride(int jj) { return cipow(L, LD - 1 - jj); } // lane digit jj (qubit R+jj)
+  // Red-black slot layout (even L).  An entry is red or black by the parity of its
+  // digit sum; every ladder term couples the two colours.  Slot i = c*H + s0*RT + t
+  // holds the entry of colour c whose leading register digit is l0 = 2*s0 + b and
+  // whose remaining register digits form t, with b = (lane parity) ^ par(t) ^ c.
+  static constexpr bool RB = (L % 2) == 0;
+  static constexpr int H = EPL / 2;              // slots per colour
+  static constexpr int HALF = L / 2;             // values of s0
+  static constexpr int RT = EPL / L;             // tuples of register digits 1..R-1
+  static constexpr int tpar(int t) { return t == 0 ? 0 : (tpar(t / L) ^ ((t % L) & 1)); }
+  static_assert(!RB || R >= 1, "red-black layout needs a register digit");
 };
 
 // Blocks are dealt to the 8 XCDs round-robin; map consecutive work items
@@ -132,10 +146,14 @@ __device__ __forceinline__ T lane_shift(T v, int src) {
 template <typename T, int Q, int L, int LD>
 struct Lane {
   using G = Geo<T, Q, L, LD>;
-  int lane, sub, col;
+  static constexpr int NH = G::RB ? G::HALF : 1;
+  int lane, sub, col, par;
   bool valid;
   int up[LD > 0 ? LD : 1], dn[LD > 0 ? LD : 1];     // permute sources for lane digits
   T wlo[LD > 0 ? LD : 1], whi[LD > 0 ? LD : 1];     // sqrt(l+1) (0 at the top level), sqrt(l) (0 at l = 0)
+  // red-black layout: ladder weights on the leading register digit for an output
+  // slot (s0, class beta), l0 = 2*s0 + (par ^ beta): sqrt(l0+1) and sqrt(l0), 0 off the ends
+  T wup[2][NH], wdn[2][NH];
   T dr[G::EPL], di[G::EPL];                         // D^{-1} per entry
   // D^{-1} - 1 split into a rounded part and its remainder.  The same factor
   // multiplies every step, so in FP32 its rounding error would accumulate
@@ -148,18 +166,28 @@ struct Lane {
     sub = lane % G::LPCP;
     col = cg * G::CPW + slot;
     valid = (sub < G::LPC) && (col < s.E);
+    par = 0;
 #pragma unroll
     for (int jj = 0; jj < LD; ++jj) {
       const int st = G::lstride(jj);
       const int l = valid ? (sub / st) % L : 0;
+      par ^= l & 1;
       up[jj] = (valid && l < L - 1) ? lane + st : lane;
       dn[jj] = (valid && l > 0) ? lane - st : lane;
       wlo[jj] = (valid && l < L - 1) ? (T)sqrt((double)(l + 1)) : (T)0;
       whi[jj] = (valid && l > 0) ? (T)sqrt((double)l) : (T)0;
     }
 #pragma unroll
+    for (int beta = 0; beta < 2; ++beta)
+#pragma unroll
+      for (int s0 = 0; s0 < NH; ++s0) {
+        const int l0 = 2 * s0 + (par ^ beta);
+        wup[beta][s0] = (valid && l0 < L - 1) ? (T)sqrt((double)(l0 + 1)) : (T)0;
+        wdn[beta][s0] = (valid && l0 > 0) ? (T)sqrt((double)l0) : (T)0;
+      }
+#pragma unroll
     for (int e = 0; e < G::EPL; ++e) {
-      const int r = e * G::LPC + sub;
+      const int r = row(e);
       const double a = valid ? s.dinv[2 * r] : 1.0, b = valid ? s.dinv[2 * r + 1] : 0.0;
       dr[e] = (T)a;
       di[e] = (T)b;
@@ -169,7 +197,16 @@ struct Lane {
       mil[e] = (T)(b - (double)mi[e]);
     }
   }
-  __device__ __forceinline__ int row(int e) const { return e * G::LPC + sub; }
+  // row of the state column held in register slot e
+  __device__ __forceinline__ int row(int e) const {
+    if constexpr (G::RB) {
+      const int c = e / G::H, s0 = (e % G::H) / G::RT, t = e % G::RT;
+      const int l0 = 2 * s0 + (par ^ G::tpar(t) ^ c);
+      return (l0 * G::RT + t) * G::LPC + sub;
+    } else {
+      return e * G::LPC + sub;
+    }
+  }
   // x = (D^{-1} - 1) u  (CONJ: (conj(D)^{-1} - 1) u), remainder first.
   template <bool CONJ>
   __device__ __forceinline__ void scale_m1(int e, T ur, T ui, T &xr, T &xi) const {
@@ -230,64 +267,197 @@ __device__ __forceinline__ void apply_Hc(const Lane<T, Q, L, LD> &ln, const T *c
 }
 
 // Per-step control coefficients: c'_j for register digits, per-lane lowering
-// (c'_j sqrt(l+1)) and raising (conj(c'_j) sqrt(l)) coefficients for lane digits.
+// (c'_j sqrt(l+1)) and raising (conj(c'_j) sqrt(l)) coefficients for lane digits,
+// and in the red-black layout the lane's coefficients on the leading register digit.
 template <typename T, int Q, int L, int LD>
-__device__ __forceinline__ void step_coeffs(const Lane<T, Q, L, LD> &ln, const T *ctrl, long long k, T *cr, T *ci,
-                                            T *lor, T *loi, T *hir, T *hii) {
+struct Coef {
+  static constexpr int NL = LD > 0 ? LD : 1, NH = Lane<T, Q, L, LD>::NH;
+  T cr[Q], ci[Q], lor[NL], loi[NL], hir[NL], hii[NL];
+  T ur[2][NH], ui[2][NH], dr[2][NH], di[2][NH];
+};
+
+template <typename T, int Q, int L, int LD>
+__device__ __forceinline__ void step_coeffs(const Lane<T, Q, L, LD> &ln, const T *ctrl, long long k,
+                                            Coef<T, Q, L, LD> &c) {
   using V2 = typename C2<T>::type;
-  const V2 *c = reinterpret_cast<const V2 *>(ctrl) + k * Q;
+  const V2 *cp = reinterpret_cast<const V2 *>(ctrl) + k * Q;
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
-    const V2 v = c[j];
-    cr[j] = v.x;
-    ci[j] = v.y;
+    const V2 v = cp[j];
+    c.cr[j] = v.x;
+    c.ci[j] = v.y;
   }
 #pragma unroll
   for (int jj = 0; jj < LD; ++jj) {
     const int j = Geo<T, Q, L, LD>::R + jj;
-    lor[jj] = cr[j] * ln.wlo[jj];
-    loi[jj] = ci[j] * ln.wlo[jj];
-    hir[jj] = cr[j] * ln.whi[jj];
-    hii[jj] = -ci[j] * ln.whi[jj];
+    c.lor[jj] = c.cr[j] * ln.wlo[jj];
+    c.loi[jj] = c.ci[j] * ln.wlo[jj];
+    c.hir[jj] = c.cr[j] * ln.whi[jj];
+    c.hii[jj] = -c.ci[j] * ln.whi[jj];
   }
+  if constexpr (Geo<T, Q, L, LD>::RB) {
+#pragma unroll
+    for (int beta = 0; beta < 2; ++beta)
+#pragma unroll
+      for (int s0 = 0; s0 < Coef<T, Q, L, LD>::NH; ++s0) {
+        c.ur[beta][s0] = c.cr[0] * ln.wup[beta][s0];
+        c.ui[beta][s0] = c.ci[0] * ln.wup[beta][s0];
+        c.dr[beta][s0] = c.cr[0] * ln.wdn[beta][s0];
+        c.di[beta][s0] = c.ci[0] * ln.wdn[beta][s0];
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------- red-black half sweep
+
+// Operands of the leading register digit for the output slots (s0, t) of one colour:
+// with X[u] the input-colour slot (u, t) and b the output's l0 parity, the upper
+// neighbour l0+1 sits in X[s0+b] and the lower one l0-1 in X[s0-1+b].  P[u+1] =
+// X[u+b] for u = -1..HALF-1 (one lane-masked select per interior u; the two end
+// values only meet zero weights when they would fall outside the digit).
+template <typename T, int HALF>
+__device__ __forceinline__ void lead_operands(bool b, const T *xr, const T *xi, int stride, T *pr, T *pi) {
+  pr[0] = xr[0];
+  pi[0] = xi[0];
+#pragma unroll
+  for (int u = 0; u + 1 < HALF; ++u) {
+    pr[u + 1] = b ? xr[(u + 1) * stride] : xr[u * stride];
+    pi[u + 1] = b ? xi[(u + 1) * stride] : xi[u * stride];
+  }
+  pr[HALF] = xr[(HALF - 1) * stride];
+  pi[HALF] = xi[(HALF - 1) * stride];
+}
+
+// Lane-digit terms of the half sweep: output slot o reads slot IN + o of the lanes
+// one digit step up and down (the colour flips with the lane parity).
+template <typename T, int Q, int L, int LD, int IN, int JJ = 0>
+__device__ __forceinline__ void half_lane_digits(const Lane<T, Q, L, LD> &ln, const Coef<T, Q, L, LD> &cf,
+                                                 const T *vr, const T *vi, T *Sr, T *Si) {
+  using G = Geo<T, Q, L, LD>;
+  if constexpr (JJ < LD) {
+    constexpr int ST = G::lstride(JJ);
+#pragma unroll
+    for (int o = 0; o < G::H; ++o) {
+      const T ur = lane_shift<T, L, ST, true>(vr[IN + o], ln.up[JJ]), ui = lane_shift<T, L, ST, true>(vi[IN + o], ln.up[JJ]);
+      const T dr_ = lane_shift<T, L, ST, false>(vr[IN + o], ln.dn[JJ]), di_ = lane_shift<T, L, ST, false>(vi[IN + o], ln.dn[JJ]);
+      cmac(Sr[o], Si[o], cf.lor[JJ], cf.loi[JJ], ur, ui);
+      cmac(Sr[o], Si[o], cf.hir[JJ], cf.hii[JJ], dr_, di_);
+    }
+    half_lane_digits<T, Q, L, LD, IN, JJ + 1>(ln, cf, vr, vi, Sr, Si);
+  }
+}
+
+// S = (dt/2) H_c v on the H slots of colour C, reading only the slots of colour 1-C.
+template <typename T, int Q, int L, int LD, int C>
+__device__ __forceinline__ void apply_half(const Lane<T, Q, L, LD> &ln, const Coef<T, Q, L, LD> &cf,
+                                           const T *vr, const T *vi, T *Sr, T *Si) {
+  using G = Geo<T, Q, L, LD>;
+  constexpr int IN = (1 - C) * G::H;
+#pragma unroll
+  for (int t = 0; t < G::RT; ++t) {            // leading register digit
+    const int beta = G::tpar(t) ^ C;
+    T pr[G::HALF + 1], pi[G::HALF + 1];
+    lead_operands<T, G::HALF>(ln.par ^ beta, vr + IN + t, vi + IN + t, G::RT, pr, pi);
+#pragma unroll
+    for (int s0 = 0; s0 < G::HALF; ++s0) {
+      const int o = s0 * G::RT + t;
+      Sr[o] = 0;
+      Si[o] = 0;
+      cmac(Sr[o], Si[o], cf.ur[beta][s0], cf.ui[beta][s0], pr[s0 + 1], pi[s0 + 1]);
+      cmac_conj(Sr[o], Si[o], cf.dr[beta][s0], cf.di[beta][s0], pr[s0], pi[s0]);
+    }
+  }
+#pragma unroll
+  for (int j = 1; j < G::R; ++j) {             // other register digits: same s0, tuple t +- stride
+    const int st = G::rstride(j);
+#pragma unroll
+    for (int o = 0; o < G::H; ++o) {
+      const int l = (o % G::RT / st) % L;
+      if (l < L - 1) {
+        const T ar = cf.cr[j] * (T)sqrt((double)(l + 1)), ai = cf.ci[j] * (T)sqrt((double)(l + 1));
+        cmac(Sr[o], Si[o], ar, ai, vr[IN + o + st], vi[IN + o + st]);
+      }
+      if (l > 0) {
+        const T ar = cf.cr[j] * (T)sqrt((double)l), ai = cf.ci[j] * (T)sqrt((double)l);
+        cmac_conj(Sr[o], Si[o], ar, ai, vr[IN + o - st], vi[IN + o - st]);
+      }
+    }
+  }
+  half_lane_digits<T, Q, L, LD, IN>(ln, cf, vr, vi, Sr, Si);
 }
 
 __device__ __forceinline__ int kit_of(const DevSys &s) { return s.kit_fixed > 0 ? s.kit_fixed : *s.kit; }
 
+// w = x - sg i D^{-1} S on the given slots (sg = +1 forward, -1 reverse/adjoint, with conj(D)).
+template <typename T, int Q, int L, int LD, bool REV>
+__device__ __forceinline__ void jacobi_update(const Lane<T, Q, L, LD> &ln, int e, T Sr, T Si, T xr, T xi, T &wr,
+                                              T &wi) {
+  if (!REV) {   // w = x - i D^{-1} S
+    wr = fma_(ln.dr[e], Si, fma_(ln.di[e], Sr, xr));
+    wi = fma_(-ln.dr[e], Sr, fma_(ln.di[e], Si, xi));
+  } else {      // w = x + i conj(D)^{-1} S
+    wr = fma_(-ln.dr[e], Si, fma_(ln.di[e], Sr, xr));
+    wi = fma_(ln.dr[e], Sr, fma_(ln.di[e], Si, xi));
+  }
+}
+
+// Red-black half sweep: refresh the increment on the slots of colour C from the
+// current values of colour 1-C.
+template <typename T, int Q, int L, int LD, bool REV, int C>
+__device__ __forceinline__ void half_sweep(const Lane<T, Q, L, LD> &ln, const Coef<T, Q, L, LD> &cf, const T *ur,
+                                           const T *ui, const T *xr, const T *xi, T *wr, T *wi) {
+  using G = Geo<T, Q, L, LD>;
+  constexpr int IN = (1 - C) * G::H, OUT = C * G::H;
+  T vr[G::EPL], vi[G::EPL], Sr[G::H], Si[G::H];
+#pragma unroll
+  for (int o = 0; o < G::H; ++o) {
+    vr[IN + o] = ur[IN + o] + wr[IN + o];
+    vi[IN + o] = ui[IN + o] + wi[IN + o];
+  }
+  apply_half<T, Q, L, LD, C>(ln, cf, vr, vi, Sr, Si);
+#pragma unroll
+  for (int o = 0; o < G::H; ++o)
+    jacobi_update<T, Q, L, LD, REV>(ln, OUT + o, Sr[o], Si[o], xr[OUT + o], xi[OUT + o], wr[OUT + o], wi[OUT + o]);
+}
+
 // One implicit-midpoint solve for the increment w = z - u, with z the solution of
 // (I + sg i dt/2 H) z = u (sg = +1 forward, -1 reverse/adjoint).  With
 // D = I + sg i dt/2 diag(h):  w = (D^{-1} - 1) u - sg i D^{-1} (dt/2) H_c (u + w),
-// iterated kit times from w = (D^{-1} - 1) u (the Jacobi splitting of the solve).
+// started from w = (D^{-1} - 1) u.  Odd L: nit Jacobi iterations (every entry from
+// the previous iterate).  Even L: H_c only couples entries of opposite digit-sum
+// parity, so the two colours are refreshed alternately, each from the other's
+// newest values; nit counts these half sweeps, each costing half an iteration.
 // The increment is O(dt |H|) |u| small, so its FP32 rounding enters the FP64
 // state only at that scale.
 template <typename T, int Q, int L, int LD, bool REV>
-__device__ __forceinline__ void solve_increment(const Lane<T, Q, L, LD> &ln, int kit, const T *cr, const T *ci,
-                                                const T *lor, const T *loi, const T *hir, const T *hii,
+__device__ __forceinline__ void solve_increment(const Lane<T, Q, L, LD> &ln, int nit, const Coef<T, Q, L, LD> &cf,
                                                 const T *ur, const T *ui, T *wr, T *wi) {
   using G = Geo<T, Q, L, LD>;
-  T xr[G::EPL], xi[G::EPL], vr[G::EPL], vi[G::EPL], Sr[G::EPL], Si[G::EPL];
+  T xr[G::EPL], xi[G::EPL];
 #pragma unroll
   for (int e = 0; e < G::EPL; ++e) {
     ln.template scale_m1<REV>(e, ur[e], ui[e], xr[e], xi[e]);
     wr[e] = xr[e];
     wi[e] = xi[e];
   }
-  for (int it = 0; it < kit; ++it) {
-#pragma unroll
-    for (int e = 0; e < G::EPL; ++e) {
-      vr[e] = ur[e] + wr[e];
-      vi[e] = ui[e] + wi[e];
+  if constexpr (G::RB) {
+    int h = 0;
+    for (; h + 1 < nit; h += 2) {
+      half_sweep<T, Q, L, LD, REV, 0>(ln, cf, ur, ui, xr, xi, wr, wi);
+      half_sweep<T, Q, L, LD, REV, 1>(ln, cf, ur, ui, xr, xi, wr, wi);
     }
-    apply_Hc<T, Q, L, LD>(ln, cr, ci, lor, loi, hir, hii, vr, vi, Sr, Si);
+    if (h < nit) half_sweep<T, Q, L, LD, REV, 0>(ln, cf, ur, ui, xr, xi, wr, wi);
+  } else {
+    T vr[G::EPL], vi[G::EPL], Sr[G::EPL], Si[G::EPL];
+    for (int it = 0; it < nit; ++it) {
 #pragma unroll
-    for (int e = 0; e < G::EPL; ++e) {
-      if (!REV) {   // w = x - i D^{-1} S
-        wr[e] = fma_(ln.dr[e], Si[e], fma_(ln.di[e], Sr[e], xr[e]));
-        wi[e] = fma_(-ln.dr[e], Sr[e], fma_(ln.di[e], Si[e], xi[e]));
-      } else {      // w = x + i conj(D)^{-1} S
-        wr[e] = fma_(-ln.dr[e], Si[e], fma_(ln.di[e], Sr[e], xr[e]));
-        wi[e] = fma_(ln.dr[e], Sr[e], fma_(ln.di[e], Si[e], xi[e]));
+      for (int e = 0; e < G::EPL; ++e) {
+        vr[e] = ur[e] + wr[e];
+        vi[e] = ui[e] + wi[e];
       }
+      apply_Hc<T, Q, L, LD>(ln, cf.cr, cf.ci, cf.lor, cf.loi, cf.hir, cf.hii, vr, vi, Sr, Si);
+#pragma unroll
+      for (int e = 0; e < G::EPL; ++e) jacobi_update<T, Q, L, LD, REV>(ln, e, Sr[e], Si[e], xr[e], xi[e], wr[e], wi[e]);
     }
   }
 }
@@ -335,15 +505,15 @@ __device__ __forceinline__ void forward_item(const DevSys &s, int m, int cg, dou
 #pragma unroll
         for (int e = 0; e < G::EPL; ++e) cp[ln.row(e)] = double2{udr[e], udi[e]};
     }
-    T cr[Q], ci[Q], lor[LD > 0 ? LD : 1], loi[LD > 0 ? LD : 1], hir[LD > 0 ? LD : 1], hii[LD > 0 ? LD : 1];
-    step_coeffs<T, Q, L, LD>(ln, ctrl, k, cr, ci, lor, loi, hir, hii);
+    Coef<T, Q, L, LD> cf;
+    step_coeffs<T, Q, L, LD>(ln, ctrl, k, cf);
     T ur[G::EPL], ui[G::EPL], wr[G::EPL], wi[G::EPL];
 #pragma unroll
     for (int e = 0; e < G::EPL; ++e) {
       ur[e] = (T)udr[e];
       ui[e] = (T)udi[e];
     }
-    solve_increment<T, Q, L, LD, false>(ln, kit, cr, ci, lor, loi, hir, hii, ur, ui, wr, wi);
+    solve_increment<T, Q, L, LD, false>(ln, kit, cf, ur, ui, wr, wi);
 #pragma unroll
     for (int e = 0; e < G::EPL; ++e) {   // u_{k+1} = 2 z - u_k = u_k + 2 w
       udr[e] += 2.0 * (double)wr[e];
@@ -374,6 +544,92 @@ __global__ __launch_bounds__(64) void k_forward(DevSys s, double *Wout, double *
   else forward_item<T, Q, L, LD, false>(s, item / s.ncg, item % s.ncg, nullptr, nullptr);
 }
 
+// Slot holding, in the lane one lane-digit step away, the row with the same
+// register digits: the other colour's slot in the red-black layout.
+template <typename G>
+__device__ __forceinline__ constexpr int partner(int e) {
+  if constexpr (G::RB) return e < G::H ? e + G::H : e - G::H;
+  else return e;
+}
+
+// Pair terms of the per-step inner products for rows e (digit l) and f (digit l+1):
+// a1 = Im(conj(y_e) z_f + conj(y_f) z_e), a2 = Re(conj(y_e) z_f - conj(y_f) z_e).
+template <typename T>
+__device__ __forceinline__ void pair_terms(T yer, T yei, T zer, T zei, T yfr, T yfi, T zfr, T zfi, T &a1, T &a2) {
+  a1 = yer * zfi;
+  a2 = yer * zfr;
+  a1 = fma_(-yei, zfr, a1); a1 = fma_(yfr, zei, a1); a1 = fma_(-yfi, zer, a1);
+  a2 = fma_(yei, zfi, a2); a2 = fma_(-yfr, zer, a2); a2 = fma_(-yfi, zei, a2);
+}
+
+// Register-digit part of the per-step inner products (see backward_item).
+template <typename T, int Q, int L, int LD>
+__device__ __forceinline__ void inner_register_digits(const Lane<T, Q, L, LD> &ln, const T *zr, const T *zi,
+                                                      const T *yr, const T *yi, T *s1, T *s2) {
+  using G = Geo<T, Q, L, LD>;
+#pragma unroll
+  for (int j = 0; j < G::R; ++j) {
+    s1[j] = 0;
+    s2[j] = 0;
+  }
+  if constexpr (G::RB) {
+    // leading digit, pairs enumerated from the red slots: (red, upper black) with
+    // weight sqrt(l0+1) and (lower black, red) with weight sqrt(l0)
+#pragma unroll
+    for (int t = 0; t < G::RT; ++t) {
+      const int beta = G::tpar(t);
+      T pzr[G::HALF + 1], pzi[G::HALF + 1], pyr[G::HALF + 1], pyi[G::HALF + 1];
+      lead_operands<T, G::HALF>(ln.par ^ beta, zr + G::H + t, zi + G::H + t, G::RT, pzr, pzi);
+      lead_operands<T, G::HALF>(ln.par ^ beta, yr + G::H + t, yi + G::H + t, G::RT, pyr, pyi);
+#pragma unroll
+      for (int s0 = 0; s0 < G::HALF; ++s0) {
+        const int e = s0 * G::RT + t;
+        T u1, u2, d1, d2;
+        pair_terms(yr[e], yi[e], zr[e], zi[e], pyr[s0 + 1], pyi[s0 + 1], pzr[s0 + 1], pzi[s0 + 1], u1, u2);
+        pair_terms(yr[e], yi[e], zr[e], zi[e], pyr[s0], pyi[s0], pzr[s0], pzi[s0], d1, d2);
+        s1[0] = fma_(ln.wup[beta][s0], u1, s1[0]);
+        s1[0] = fma_(ln.wdn[beta][s0], d1, s1[0]);
+        s2[0] = fma_(ln.wup[beta][s0], u2, s2[0]);
+        s2[0] = fma_(-ln.wdn[beta][s0], d2, s2[0]);
+      }
+    }
+    // other register digits: slot e (digit l < L-1) pairs with the other colour's
+    // slot at tuple t + stride
+#pragma unroll
+    for (int j = 1; j < G::R; ++j) {
+      const int st = G::rstride(j);
+#pragma unroll
+      for (int e = 0; e < G::EPL; ++e) {
+        const int l = (e % G::RT / st) % L;
+        if (l < L - 1) {
+          const int f = partner<G>(e) + st;
+          T a1, a2;
+          pair_terms(yr[e], yi[e], zr[e], zi[e], yr[f], yi[f], zr[f], zi[f], a1, a2);
+          const T w = (T)sqrt((double)(l + 1));
+          s1[j] = fma_(w, a1, s1[j]);
+          s2[j] = fma_(w, a2, s2[j]);
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < G::R; ++j) {
+#pragma unroll
+      for (int e = 0; e < G::EPL; ++e) {
+        const int l = G::rdigit(e, j);
+        if (l < L - 1) {
+          const int f = e + G::rstride(j);
+          T a1, a2;
+          pair_terms(yr[e], yi[e], zr[e], zi[e], yr[f], yi[f], zr[f], zi[f], a1, a2);
+          const T w = (T)sqrt((double)(l + 1));
+          s1[j] = fma_(w, a1, s1[j]);
+          s2[j] = fma_(w, a2, s2[j]);
+        }
+      }
+    }
+  }
+}
+
 // Lane-digit part of the per-step inner products.
 template <typename T, int Q, int L, int LD, int JJ = 0>
 __device__ __forceinline__ void inner_lane_digits(const Lane<T, Q, L, LD> &ln, const T *zr, const T *zi, const T *yr,
@@ -384,8 +640,9 @@ __device__ __forceinline__ void inner_lane_digits(const Lane<T, Q, L, LD> &ln, c
     T a1 = 0, a2 = 0;
 #pragma unroll
     for (int e = 0; e < G::EPL; ++e) {
-      const T zur = lane_shift<T, L, ST, true>(zr[e], ln.up[JJ]), zui = lane_shift<T, L, ST, true>(zi[e], ln.up[JJ]);
-      const T yur = lane_shift<T, L, ST, true>(yr[e], ln.up[JJ]), yui = lane_shift<T, L, ST, true>(yi[e], ln.up[JJ]);
+      const int f = partner<G>(e);   // the same row of the lane one digit step up
+      const T zur = lane_shift<T, L, ST, true>(zr[f], ln.up[JJ]), zui = lane_shift<T, L, ST, true>(zi[f], ln.up[JJ]);
+      const T yur = lane_shift<T, L, ST, true>(yr[f], ln.up[JJ]), yui = lane_shift<T, L, ST, true>(yi[f], ln.up[JJ]);
       a1 = fma_(yr[e], zui, a1); a1 = fma_(-yi[e], zur, a1); a1 = fma_(yur, zi[e], a1); a1 = fma_(-yui, zr[e], a1);
       a2 = fma_(yr[e], zur, a2); a2 = fma_(yi[e], zui, a2); a2 = fma_(-yur, zr[e], a2); a2 = fma_(-yui, zi[e], a2);
     }
@@ -462,8 +719,8 @@ __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T 
   double *ser = s.series + (size_t)item * s.maxlen * 2 * Q;
 
   for (long long k = k1 - 1; k >= k0; --k) {
-    T cr[Q], ci[Q], lor[LD > 0 ? LD : 1], loi[LD > 0 ? LD : 1], hir[LD > 0 ? LD : 1], hii[LD > 0 ? LD : 1];
-    step_coeffs<T, Q, L, LD>(ln, ctrl, k, cr, ci, lor, loi, hir, hii);
+    Coef<T, Q, L, LD> cf;
+    step_coeffs<T, Q, L, LD>(ln, ctrl, k, cf);
     T ur[G::EPL], ui[G::EPL], lr[G::EPL], li[G::EPL];
     T wur[G::EPL], wui[G::EPL], wlr[G::EPL], wli[G::EPL];
 #pragma unroll
@@ -473,8 +730,8 @@ __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T 
       lr[e] = (T)ldr[e];
       li[e] = (T)ldi[e];
     }
-    solve_increment<T, Q, L, LD, true>(ln, kit, cr, ci, lor, loi, hir, hii, ur, ui, wur, wui);
-    solve_increment<T, Q, L, LD, true>(ln, kit, cr, ci, lor, loi, hir, hii, lr, li, wlr, wli);
+    solve_increment<T, Q, L, LD, true>(ln, kit, cf, ur, ui, wur, wui);
+    solve_increment<T, Q, L, LD, true>(ln, kit, cf, lr, li, wlr, wli);
     T zr[G::EPL], zi[G::EPL], yr[G::EPL], yi[G::EPL];
 #pragma unroll
     for (int e = 0; e < G::EPL; ++e) {
@@ -486,24 +743,7 @@ __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T 
     // inner products per qubit: s1 = Im(A + B), s2 = Re(A - B) with
     // A = <y, a_j z> = sum conj(y_r) sqrt(l+1) z_{r+st},  B = <y, a_j^+ z> = sum sqrt(l+1) conj(y_{r+st}) z_r
     T s1[Q], s2[Q];
-#pragma unroll
-    for (int j = 0; j < G::R; ++j) {
-      s1[j] = 0;
-      s2[j] = 0;
-#pragma unroll
-      for (int e = 0; e < G::EPL; ++e) {
-        const int l = G::rdigit(e, j);
-        if (l < L - 1) {
-          const int f = e + G::rstride(j);
-          const T w = (T)sqrt((double)(l + 1));
-          T a1 = yr[e] * zi[f], a2 = yr[e] * zr[f];
-          a1 = fma_(-yi[e], zr[f], a1); a1 = fma_(yr[f], zi[e], a1); a1 = fma_(-yi[f], zr[e], a1);
-          a2 = fma_(yi[e], zi[f], a2); a2 = fma_(-yr[f], zr[e], a2); a2 = fma_(-yi[f], zi[e], a2);
-          s1[j] = fma_(w, a1, s1[j]);
-          s2[j] = fma_(w, a2, s2[j]);
-        }
-      }
-    }
+    inner_register_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
     inner_lane_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
     {
       using SB = SeriesBuf<Q>;
@@ -565,14 +805,20 @@ __global__ __launch_bounds__(64) void k_backward(DevSys s, int nitems) {
 // Fixed-point iteration count.  The Jacobi map w -> (D^{-1} - 1)u - i D^{-1} (dt/2) H_c (u + w)
 // contracts in the 2-norm by rho_k <= |D^{-1}| nu_L sum_j |c'_j(t_k)| with |D^{-1}| <= 1,
 // c'_j = (dt/2) 2 pi d_j and nu_L = ||a + a^+||_2; k_controls leaves max_k of that bound
-// in rho_bits.  Starting from w = (D^{-1} - 1)u, K iterations leave an error
-// <= rho^(K+1) |z|; K is the smallest count with rho^(K+1) <= solve_tol.
+// in rho_bits.  Starting from w = (D^{-1} - 1)u (error <= rho |z|):
+//  Jacobi (odd L): K iterations leave <= rho^(K+1) |z|; K is the smallest count with
+//    rho^(K+1) <= solve_tol.
+//  red-black (even L): each half sweep multiplies the refreshed colour's error by a
+//    block of the iteration matrix (2-norm <= rho), so after h half sweeps the colours
+//    carry <= rho^(h+1) |z| and <= rho^h |z|, together <= rho^h sqrt(1 + rho^2) |z|;
+//    h is the smallest count with that <= solve_tol.
 __device__ void kit_block(const DevSys &s) {
   if (threadIdx.x != 0) return;
   const double rho = (double)__uint_as_float(*s.rho_bits) * (1.0 + 1e-6);
   *s.rho_bits = 0u;                  // reset for the next evaluation
+  const bool rb = (s.L % 2) == 0;
   int K = 1;
-  double err = rho * rho;
+  double err = rb ? rho * sqrt(1.0 + rho * rho) : rho * rho;
   while (err > s.solve_tol && K < 64) { err *= rho; ++K; }
   if (s.kit_fixed <= 0) *s.kit = K;
   if (s.kit_fixed <= 0 && (err > s.solve_tol || rho >= 0.5)) atomicOr(s.status, (int)STATUS_NOTCONV);

@@ -1,6 +1,6 @@
 """Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
 
-Tolerances (derived in the design doc):
+Tolerances:
   FP64 propagation: P and terms to 1e-11 relative, gradients to 1e-10 in
   relative L2 (fixed-point truncation <= 2^-54 per step plus rounding-order
   differences over <= 1e5 steps).
