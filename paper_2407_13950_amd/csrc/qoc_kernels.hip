@@ -101,47 +101,89 @@ __device__ __forceinline__ double bspline2(double x) {
   return 0.0;
 }
 
-// ---------------------------------------------------------------------------- per-lane state
+// ---------------------------------------------------------------------------- lane exchange
 
-// Lane shift for lane digit jj: DPP row shift when every shifted pair stays in
-// one 16-lane row (L a power of two and the digit block L^(k+1) <= 16), else a
-// cross-lane permute through the LDS crossbar.
-// QOC_DPP_BLOCK: largest digit block (L^(k+1)) shifted with DPP; 16 = every in-row
-// shift, 4 = only the innermost digit, 1 = none (all through the LDS crossbar, which
-// keeps the VALU free for the arithmetic).
-#ifndef QOC_DPP_BLOCK
-#define QOC_DPP_BLOCK 16
-#endif
-template <int L, int ST>
-struct ShiftKind {
-  static constexpr bool pow2 = (L & (L - 1)) == 0;
-  static constexpr bool dpp = pow2 && ST * L <= 16 && ST * L <= QOC_DPP_BLOCK;
+// Lane-digit ladder terms read values held by other lanes of the wavefront.  Each
+// lane writes a record of NV values to a per-wavefront LDS buffer and reads the
+// records of the lanes +-ST away (one 16-byte access per four floats).  kGuard
+// records on both sides of the 64 lane records cover reads past the wavefront's
+// ends; the buffer is zeroed once per launch and afterwards only ever holds state
+// values, and every read outside a lane's own digit block meets a zero ladder
+// weight.  LDS operations of one wavefront complete in issue order, so the
+// exchange needs no wait, only compiler ordering (wave_sync).
+constexpr int kGuard = 16;                      // >= every lane-digit stride
+constexpr int kXchgMaxNV = 8;                   // values per record: 2*EPL with EPL <= 4
+template <typename T>
+constexpr int xchg_bytes() { return (64 + 2 * kGuard) * kXchgMaxNV * (int)sizeof(T); }
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Zero the whole exchange buffer (64 lanes, 16 bytes per store).
+template <typename T>
+__device__ __forceinline__ void xchg_clear(T *buf) {
+  float4 *p = reinterpret_cast<float4 *>(buf);
+  for (int i = threadIdx.x; i < xchg_bytes<T>() / 16; i += 64) p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  wave_sync();
+}
+
+// v[0..NV) -> record of lane `lane`;  record of lane `lane + D` -> v[0..NV).
+// Records are accessed in 16-byte pieces when their size allows it (every piece
+// then stays 16-byte aligned), else in 8-byte pieces.
+template <typename T, int NV>
+struct XRec {
+  static_assert(NV <= kXchgMaxNV && (NV * sizeof(T)) % 8 == 0, "exchange record");
+  static constexpr int BYTES = NV * (int)sizeof(T);
+  static constexpr bool WIDE = BYTES % 16 == 0;
 };
 
-template <int CTRL>
-__device__ __forceinline__ float dpp_f32(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// value of lane (lane + ST) (UP) or (lane - ST) (down); meaningful only where the
-// ladder coefficient is nonzero, i.e. where that lane holds the neighbouring row.
-template <typename T, int L, int ST, bool UP>
-__device__ __forceinline__ T lane_shift(T v, int src) {
-  if constexpr (ShiftKind<L, ST>::dpp) {
-    constexpr int ctrl = UP ? (0x100 + ST) : (0x110 + ST);   // row_shl:ST reads lane+ST, row_shr:ST reads lane-ST
-    if constexpr (sizeof(T) == 4) return dpp_f32<ctrl>(v);
-    else return dpp_f64<ctrl>(v);
+template <typename T, int NV>
+__device__ __forceinline__ void xput(T *buf, int lane, const T *v) {
+  T *p = buf + (kGuard + lane) * NV;
+  if constexpr (sizeof(T) == 4) {
+    if constexpr (XRec<T, NV>::WIDE) {
+#pragma unroll
+      for (int i = 0; i < NV; i += 4) *reinterpret_cast<float4 *>(p + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < NV; i += 2) *reinterpret_cast<float2 *>(p + i) = make_float2(v[i], v[i + 1]);
+    }
   } else {
-    return __shfl(v, src, 64);
+#pragma unroll
+    for (int i = 0; i < NV; i += 2) *reinterpret_cast<double2 *>(p + i) = make_double2(v[i], v[i + 1]);
   }
 }
+template <typename T, int NV, int D>
+__device__ __forceinline__ void xget(const T *buf, int lane, T *v) {
+  static_assert(D >= -kGuard && D <= kGuard, "lane shift beyond the guard records");
+  const T *p = buf + (kGuard + lane + D) * NV;
+  if constexpr (sizeof(T) == 4) {
+    if constexpr (XRec<T, NV>::WIDE) {
+#pragma unroll
+      for (int i = 0; i < NV; i += 4) {
+        const float4 c = *reinterpret_cast<const float4 *>(p + i);
+        v[i] = c.x; v[i + 1] = c.y; v[i + 2] = c.z; v[i + 3] = c.w;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NV; i += 2) {
+        const float2 c = *reinterpret_cast<const float2 *>(p + i);
+        v[i] = c.x; v[i + 1] = c.y;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < NV; i += 2) {
+      const double2 c = *reinterpret_cast<const double2 *>(p + i);
+      v[i] = c.x; v[i + 1] = c.y;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------- per-lane state
 
 template <typename T, int Q, int L, int LD>
 struct Lane {
@@ -149,7 +191,7 @@ struct Lane {
   static constexpr int NH = G::RB ? G::HALF : 1;
   int lane, sub, col, par;
   bool valid;
-  int up[LD > 0 ? LD : 1], dn[LD > 0 ? LD : 1];     // permute sources for lane digits
+  T *xb;                                            // this wavefront's exchange buffer (LDS)
   T wlo[LD > 0 ? LD : 1], whi[LD > 0 ? LD : 1];     // sqrt(l+1) (0 at the top level), sqrt(l) (0 at l = 0)
   // red-black layout: ladder weights on the leading register digit for an output
   // slot (s0, class beta), l0 = 2*s0 + (par ^ beta): sqrt(l0+1) and sqrt(l0), 0 off the ends
@@ -160,7 +202,8 @@ struct Lane {
   // linearly over a window; the remainder removes that drift.
   T mr[G::EPL], mi[G::EPL], mrl[G::EPL], mil[G::EPL];
 
-  __device__ void init(const DevSys &s, int cg) {
+  __device__ void init(const DevSys &s, int cg, T *xbuf) {
+    xb = xbuf;
     lane = threadIdx.x;
     const int slot = lane / G::LPCP;
     sub = lane % G::LPCP;
@@ -172,8 +215,6 @@ struct Lane {
       const int st = G::lstride(jj);
       const int l = valid ? (sub / st) % L : 0;
       par ^= l & 1;
-      up[jj] = (valid && l < L - 1) ? lane + st : lane;
-      dn[jj] = (valid && l > 0) ? lane - st : lane;
       wlo[jj] = (valid && l < L - 1) ? (T)sqrt((double)(l + 1)) : (T)0;
       whi[jj] = (valid && l > 0) ? (T)sqrt((double)l) : (T)0;
     }
@@ -221,25 +262,46 @@ struct Lane {
   }
 };
 
-// S = (dt/2) H_c v for this lane's entries.  cr/ci: per-qubit scaled control
-// c'_j = (dt/2) 2 pi d_j; the coefficient of a_j is c'_j, of a_j^+ conj(c'_j).
-template <typename T, int Q, int L, int LD, int JJ = 0>
-__device__ __forceinline__ void apply_lane_digits(const Lane<T, Q, L, LD> &ln, const T *lor, const T *loi,
-                                                  const T *hir, const T *hii, const T *vr, const T *vi, T *Sr, T *Si) {
+// Lane-digit ladder terms for K complex values per lane: for every lane digit,
+// S[o] += lo * v'[o] + hi * v''[o] with v', v'' the values o of the lanes one digit
+// step up and down (lo = c'_j sqrt(l+1), hi = conj(c'_j) sqrt(l), zero off the ends).
+template <typename T, int Q, int L, int LD, int K, int JJ>
+__device__ __forceinline__ void lane_digit_gets(const Lane<T, Q, L, LD> &ln, const T *lor, const T *loi,
+                                                const T *hir, const T *hii, T *Sr, T *Si) {
   using G = Geo<T, Q, L, LD>;
   if constexpr (JJ < LD) {
     constexpr int ST = G::lstride(JJ);
+    T n[2 * K];
+    xget<T, 2 * K, ST>(ln.xb, ln.lane, n);
 #pragma unroll
-    for (int e = 0; e < G::EPL; ++e) {
-      const T ur = lane_shift<T, L, ST, true>(vr[e], ln.up[JJ]), ui = lane_shift<T, L, ST, true>(vi[e], ln.up[JJ]);
-      const T dr_ = lane_shift<T, L, ST, false>(vr[e], ln.dn[JJ]), di_ = lane_shift<T, L, ST, false>(vi[e], ln.dn[JJ]);
-      cmac(Sr[e], Si[e], lor[JJ], loi[JJ], ur, ui);
-      cmac(Sr[e], Si[e], hir[JJ], hii[JJ], dr_, di_);
-    }
-    apply_lane_digits<T, Q, L, LD, JJ + 1>(ln, lor, loi, hir, hii, vr, vi, Sr, Si);
+    for (int o = 0; o < K; ++o) cmac(Sr[o], Si[o], lor[JJ], loi[JJ], n[2 * o], n[2 * o + 1]);
+    xget<T, 2 * K, -ST>(ln.xb, ln.lane, n);
+#pragma unroll
+    for (int o = 0; o < K; ++o) cmac(Sr[o], Si[o], hir[JJ], hii[JJ], n[2 * o], n[2 * o + 1]);
+    lane_digit_gets<T, Q, L, LD, K, JJ + 1>(ln, lor, loi, hir, hii, Sr, Si);
   }
 }
 
+template <typename T, int Q, int L, int LD, int K>
+__device__ __forceinline__ void lane_digit_terms(const Lane<T, Q, L, LD> &ln, const T *lor, const T *loi,
+                                                 const T *hir, const T *hii, const T *vr, const T *vi, T *Sr,
+                                                 T *Si) {
+  if constexpr (LD > 0) {
+    T rec[2 * K];
+#pragma unroll
+    for (int o = 0; o < K; ++o) {
+      rec[2 * o] = vr[o];
+      rec[2 * o + 1] = vi[o];
+    }
+    xput<T, 2 * K>(ln.xb, ln.lane, rec);
+    wave_sync();
+    lane_digit_gets<T, Q, L, LD, K, 0>(ln, lor, loi, hir, hii, Sr, Si);
+    wave_sync();
+  }
+}
+
+// S = (dt/2) H_c v for this lane's entries.  cr/ci: per-qubit scaled control
+// c'_j = (dt/2) 2 pi d_j; the coefficient of a_j is c'_j, of a_j^+ conj(c'_j).
 template <typename T, int Q, int L, int LD>
 __device__ __forceinline__ void apply_Hc(const Lane<T, Q, L, LD> &ln, const T *cr, const T *ci,
                                          const T *lor, const T *loi, const T *hir, const T *hii,
@@ -263,7 +325,7 @@ __device__ __forceinline__ void apply_Hc(const Lane<T, Q, L, LD> &ln, const T *c
       }
     }
   }
-  apply_lane_digits<T, Q, L, LD>(ln, lor, loi, hir, hii, vr, vi, Sr, Si);
+  lane_digit_terms<T, Q, L, LD, G::EPL>(ln, lor, loi, hir, hii, vr, vi, Sr, Si);
 }
 
 // Per-step control coefficients: c'_j for register digits, per-lane lowering
@@ -328,25 +390,6 @@ __device__ __forceinline__ void lead_operands(bool b, const T *xr, const T *xi, 
   pi[HALF] = xi[(HALF - 1) * stride];
 }
 
-// Lane-digit terms of the half sweep: output slot o reads slot IN + o of the lanes
-// one digit step up and down (the colour flips with the lane parity).
-template <typename T, int Q, int L, int LD, int IN, int JJ = 0>
-__device__ __forceinline__ void half_lane_digits(const Lane<T, Q, L, LD> &ln, const Coef<T, Q, L, LD> &cf,
-                                                 const T *vr, const T *vi, T *Sr, T *Si) {
-  using G = Geo<T, Q, L, LD>;
-  if constexpr (JJ < LD) {
-    constexpr int ST = G::lstride(JJ);
-#pragma unroll
-    for (int o = 0; o < G::H; ++o) {
-      const T ur = lane_shift<T, L, ST, true>(vr[IN + o], ln.up[JJ]), ui = lane_shift<T, L, ST, true>(vi[IN + o], ln.up[JJ]);
-      const T dr_ = lane_shift<T, L, ST, false>(vr[IN + o], ln.dn[JJ]), di_ = lane_shift<T, L, ST, false>(vi[IN + o], ln.dn[JJ]);
-      cmac(Sr[o], Si[o], cf.lor[JJ], cf.loi[JJ], ur, ui);
-      cmac(Sr[o], Si[o], cf.hir[JJ], cf.hii[JJ], dr_, di_);
-    }
-    half_lane_digits<T, Q, L, LD, IN, JJ + 1>(ln, cf, vr, vi, Sr, Si);
-  }
-}
-
 // S = (dt/2) H_c v on the H slots of colour C, reading only the slots of colour 1-C.
 template <typename T, int Q, int L, int LD, int C>
 __device__ __forceinline__ void apply_half(const Lane<T, Q, L, LD> &ln, const Coef<T, Q, L, LD> &cf,
@@ -383,7 +426,9 @@ __device__ __forceinline__ void apply_half(const Lane<T, Q, L, LD> &ln, const Co
       }
     }
   }
-  half_lane_digits<T, Q, L, LD, IN>(ln, cf, vr, vi, Sr, Si);
+  // lane digits: output slot o reads slot IN + o of the neighbouring lanes (the
+  // colour flips with the lane parity)
+  lane_digit_terms<T, Q, L, LD, G::H>(ln, cf.lor, cf.loi, cf.hir, cf.hii, vr + IN, vi + IN, Sr, Si);
 }
 
 __device__ __forceinline__ int kit_of(const DevSys &s) { return s.kit_fixed > 0 ? s.kit_fixed : *s.kit; }
@@ -470,10 +515,10 @@ __device__ __forceinline__ void solve_increment(const Lane<T, Q, L, LD> &ln, int
 // checkpoints U_{k0 + i*C} are written on the way.  ROLLOUT: a single window over
 // all steps from W^0, writing the states at the window boundaries instead.
 template <typename T, int Q, int L, int LD, bool ROLLOUT>
-__device__ __forceinline__ void forward_item(const DevSys &s, int m, int cg, double *Wout, double *Uout) {
+__device__ __forceinline__ void forward_item(const DevSys &s, int m, int cg, double *Wout, double *Uout, T *xb) {
   using G = Geo<T, Q, L, LD>;
   Lane<T, Q, L, LD> ln;
-  ln.init(s, cg);
+  ln.init(s, cg, xb);
 
   double udr[G::EPL], udi[G::EPL];
 #pragma unroll
@@ -540,8 +585,10 @@ template <typename T, int Q, int L, int LD, bool ROLLOUT>
 __global__ __launch_bounds__(64) void k_forward(DevSys s, double *Wout, double *Uout, int nitems) {
   const int item = xcd_item(blockIdx.x, gridDim.x);
   if (item >= nitems) return;
-  if (ROLLOUT) forward_item<T, Q, L, LD, true>(s, 0, item, Wout, Uout);
-  else forward_item<T, Q, L, LD, false>(s, item / s.ncg, item % s.ncg, nullptr, nullptr);
+  __shared__ __align__(16) T xb[xchg_bytes<T>() / sizeof(T)];
+  xchg_clear(xb);
+  if (ROLLOUT) forward_item<T, Q, L, LD, true>(s, 0, item, Wout, Uout, xb);
+  else forward_item<T, Q, L, LD, false>(s, item / s.ncg, item % s.ncg, nullptr, nullptr, xb);
 }
 
 // Slot holding, in the lane one lane-digit step away, the row with the same
@@ -630,25 +677,65 @@ __device__ __forceinline__ void inner_register_digits(const Lane<T, Q, L, LD> &l
   }
 }
 
-// Lane-digit part of the per-step inner products.
-template <typename T, int Q, int L, int LD, int JJ = 0>
-__device__ __forceinline__ void inner_lane_digits(const Lane<T, Q, L, LD> &ln, const T *zr, const T *zi, const T *yr,
-                                                  const T *yi, T *s1, T *s2) {
+// Lane-digit part of the per-step inner products: pairs (row in this lane, the
+// same register digits in the lane one digit step up); a1 = Im(conj(y) z' + conj(y') z),
+// a2 = Re(conj(y) z' - conj(y') z) with ' the upper lane.  z' and y' pass through
+// the exchange one after the other.
+template <typename T, int Q, int L, int LD, bool ZROUND, int JJ = 0>
+__device__ __forceinline__ void inner_lane_gets(const Lane<T, Q, L, LD> &ln, const T *zr, const T *zi,
+                                                const T *yr, const T *yi, T *a1, T *a2) {
   using G = Geo<T, Q, L, LD>;
   if constexpr (JJ < LD) {
     constexpr int ST = G::lstride(JJ);
-    T a1 = 0, a2 = 0;
+    T n[2 * G::EPL];
+    xget<T, 2 * G::EPL, ST>(ln.xb, ln.lane, n);
 #pragma unroll
     for (int e = 0; e < G::EPL; ++e) {
       const int f = partner<G>(e);   // the same row of the lane one digit step up
-      const T zur = lane_shift<T, L, ST, true>(zr[f], ln.up[JJ]), zui = lane_shift<T, L, ST, true>(zi[f], ln.up[JJ]);
-      const T yur = lane_shift<T, L, ST, true>(yr[f], ln.up[JJ]), yui = lane_shift<T, L, ST, true>(yi[f], ln.up[JJ]);
-      a1 = fma_(yr[e], zui, a1); a1 = fma_(-yi[e], zur, a1); a1 = fma_(yur, zi[e], a1); a1 = fma_(-yui, zr[e], a1);
-      a2 = fma_(yr[e], zur, a2); a2 = fma_(yi[e], zui, a2); a2 = fma_(-yur, zr[e], a2); a2 = fma_(-yui, zi[e], a2);
+      const T ur = n[2 * f], ui = n[2 * f + 1];
+      if constexpr (ZROUND) {        // z' terms: conj(y) z'
+        a1[JJ] = fma_(yr[e], ui, a1[JJ]); a1[JJ] = fma_(-yi[e], ur, a1[JJ]);
+        a2[JJ] = fma_(yr[e], ur, a2[JJ]); a2[JJ] = fma_(yi[e], ui, a2[JJ]);
+      } else {                       // y' terms: conj(y') z
+        a1[JJ] = fma_(ur, zi[e], a1[JJ]); a1[JJ] = fma_(-ui, zr[e], a1[JJ]);
+        a2[JJ] = fma_(-ur, zr[e], a2[JJ]); a2[JJ] = fma_(-ui, zi[e], a2[JJ]);
+      }
     }
-    s1[G::R + JJ] = ln.wlo[JJ] * a1;
-    s2[G::R + JJ] = ln.wlo[JJ] * a2;
-    inner_lane_digits<T, Q, L, LD, JJ + 1>(ln, zr, zi, yr, yi, s1, s2);
+    inner_lane_gets<T, Q, L, LD, ZROUND, JJ + 1>(ln, zr, zi, yr, yi, a1, a2);
+  }
+}
+
+template <typename T, int Q, int L, int LD>
+__device__ __forceinline__ void inner_lane_digits(const Lane<T, Q, L, LD> &ln, const T *zr, const T *zi, const T *yr,
+                                                  const T *yi, T *s1, T *s2) {
+  using G = Geo<T, Q, L, LD>;
+  if constexpr (LD > 0) {
+    T a1[LD], a2[LD], rec[2 * G::EPL];
+#pragma unroll
+    for (int jj = 0; jj < LD; ++jj) a1[jj] = a2[jj] = 0;
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {
+      rec[2 * e] = zr[e];
+      rec[2 * e + 1] = zi[e];
+    }
+    xput<T, 2 * G::EPL>(ln.xb, ln.lane, rec);
+    wave_sync();
+    inner_lane_gets<T, Q, L, LD, true>(ln, zr, zi, yr, yi, a1, a2);
+    wave_sync();
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {
+      rec[2 * e] = yr[e];
+      rec[2 * e + 1] = yi[e];
+    }
+    xput<T, 2 * G::EPL>(ln.xb, ln.lane, rec);
+    wave_sync();
+    inner_lane_gets<T, Q, L, LD, false>(ln, zr, zi, yr, yi, a1, a2);
+    wave_sync();
+#pragma unroll
+    for (int jj = 0; jj < LD; ++jj) {
+      s1[G::R + jj] = ln.wlo[jj] * a1[jj];
+      s2[G::R + jj] = ln.wlo[jj] * a2[jj];
+    }
   }
 }
 
@@ -658,13 +745,14 @@ __device__ __forceinline__ void inner_lane_digits(const Lane<T, Q, L, LD> &ln, c
 // every step each lane stores its 2q partial sums (propagation precision); every RB steps
 // lane i sums, in FP64 and in lane order, the 64 partials of one (step, value)
 // pair and writes it to the series (one coalesced store per flush).
-constexpr int kRedFloats = 36 * 64;             // LDS elements per wavefront (all q)
+template <typename T>
+constexpr int red_elems() { return sizeof(T) == 4 ? 36 * 64 : 24 * 64; }   // 9 KB (FP32), 12 KB (FP64) per wavefront
 
-template <int Q>
+template <typename T, int Q>
 struct SeriesBuf {
   static constexpr int NV = 2 * Q;               // values per step
   static constexpr int RS = 64 * NV + 8;         // elements per buffered step (padded)
-  static constexpr int RB = (kRedFloats / RS < 64 / NV) ? kRedFloats / RS : 64 / NV;   // steps per flush
+  static constexpr int RB = (red_elems<T>() / RS < 64 / NV) ? red_elems<T>() / RS : 64 / NV;   // steps per flush
   static_assert(RB >= 1, "reduction buffer too small");
 };
 
@@ -683,11 +771,11 @@ struct SeriesBuf {
 // propagated, and the W-gradient adds the dropped part back exactly:
 // Lambda^M(t_{M-1}) = -W^{M-1}/E + (propagated part)  (App. B, eq. back-prop-2).
 template <typename T, int Q, int L, int LD>
-__device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T *red) {
+__device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T *red, T *xb) {
   using G = Geo<T, Q, L, LD>;
   const int item = m * s.ncg + cg;
   Lane<T, Q, L, LD> ln;
-  ln.init(s, cg);
+  ln.init(s, cg, xb);
 
   double udr[G::EPL], udi[G::EPL], ldr[G::EPL], ldi[G::EPL];
   {
@@ -746,7 +834,7 @@ __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T 
     inner_register_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
     inner_lane_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
     {
-      using SB = SeriesBuf<Q>;
+      using SB = SeriesBuf<T, Q>;
       const int idx = (int)(k - k0);
       T *slot = red + (idx % SB::RB) * SB::RS + ln.lane * SB::NV;
 #pragma unroll
@@ -796,8 +884,10 @@ template <typename T, int Q, int L, int LD>
 __global__ __launch_bounds__(64) void k_backward(DevSys s, int nitems) {
   const int item = xcd_item(blockIdx.x, gridDim.x);
   if (item >= nitems) return;
-  __shared__ T red[kRedFloats];
-  backward_item<T, Q, L, LD>(s, item / s.ncg, item % s.ncg, red);
+  __shared__ T red[red_elems<T>()];
+  __shared__ __align__(16) T xb[xchg_bytes<T>() / sizeof(T)];
+  xchg_clear(xb);
+  backward_item<T, Q, L, LD>(s, item / s.ncg, item % s.ncg, red, xb);
 }
 
 // ---------------------------------------------------------------------------- small FP64 kernels
@@ -1069,11 +1159,13 @@ bool lookup(int q, int L, Kernels *k, int *ld, int *cpw, int *shape) {
 // items ordered by the host (longest first).
 template <typename T>
 __global__ __launch_bounds__(64) void k_forward_batch(const DevSys *sys, const int4 *items) {
+  __shared__ __align__(16) T xb[xchg_bytes<T>() / sizeof(T)];
+  xchg_clear(xb);
   const int4 it = items[blockIdx.x];
   const DevSys s = sys[it.x];
   switch (it.w) {
 #define X(Q_, L_, LD_) \
-    case SHAPE_##Q_##_##L_: forward_item<T, Q_, L_, LD_, false>(s, it.y, it.z, nullptr, nullptr); break;
+    case SHAPE_##Q_##_##L_: forward_item<T, Q_, L_, LD_, false>(s, it.y, it.z, nullptr, nullptr, xb); break;
     QOC_SHAPES(X)
 #undef X
     default: break;
@@ -1082,12 +1174,14 @@ __global__ __launch_bounds__(64) void k_forward_batch(const DevSys *sys, const i
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_backward_batch(const DevSys *sys, const int4 *items) {
-  __shared__ T red[kRedFloats];
+  __shared__ T red[red_elems<T>()];
+  __shared__ __align__(16) T xb[xchg_bytes<T>() / sizeof(T)];
+  xchg_clear(xb);
   const int4 it = items[blockIdx.x];
   const DevSys s = sys[it.x];
   switch (it.w) {
 #define X(Q_, L_, LD_) \
-    case SHAPE_##Q_##_##L_: backward_item<T, Q_, L_, LD_>(s, it.y, it.z, red); break;
+    case SHAPE_##Q_##_##L_: backward_item<T, Q_, L_, LD_>(s, it.y, it.z, red, xb); break;
     QOC_SHAPES(X)
 #undef X
     default: break;
