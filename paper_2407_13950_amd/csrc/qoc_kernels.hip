@@ -265,27 +265,31 @@ struct Lane {
 // Lane-digit ladder terms for K complex values per lane: for every lane digit,
 // S[o] += lo * v'[o] + hi * v''[o] with v', v'' the values o of the lanes one digit
 // step up and down (lo = c'_j sqrt(l+1), hi = conj(c'_j) sqrt(l), zero off the ends).
-template <typename T, int Q, int L, int LD, int K, int JJ>
-__device__ __forceinline__ void lane_digit_gets(const Lane<T, Q, L, LD> &ln, const T *lor, const T *loi,
-                                                const T *hir, const T *hii, T *Sr, T *Si) {
-  using G = Geo<T, Q, L, LD>;
-  if constexpr (JJ < LD) {
-    constexpr int ST = G::lstride(JJ);
-    T n[2 * K];
-    xget<T, 2 * K, ST>(ln.xb, ln.lane, n);
-#pragma unroll
-    for (int o = 0; o < K; ++o) cmac(Sr[o], Si[o], lor[JJ], loi[JJ], n[2 * o], n[2 * o + 1]);
-    xget<T, 2 * K, -ST>(ln.xb, ln.lane, n);
-#pragma unroll
-    for (int o = 0; o < K; ++o) cmac(Sr[o], Si[o], hir[JJ], hii[JJ], n[2 * o], n[2 * o + 1]);
-    lane_digit_gets<T, Q, L, LD, K, JJ + 1>(ln, lor, loi, hir, hii, Sr, Si);
+// All neighbour records are requested before the first is used, so their LDS
+// latencies overlap.
+template <typename T, int LD, int K, int JJ>
+struct LaneGets {
+  template <typename LaneT>
+  __device__ __forceinline__ static void load(const LaneT &ln, T (*n)[2 * K]) {
+    if constexpr (JJ < LD) {
+      constexpr int ST = LaneT::G::lstride(JJ);
+      xget<T, 2 * K, ST>(ln.xb, ln.lane, n[2 * JJ]);
+      xget<T, 2 * K, -ST>(ln.xb, ln.lane, n[2 * JJ + 1]);
+      LaneGets<T, LD, K, JJ + 1>::load(ln, n);
+    }
   }
-}
+};
+
+// Writes this lane's K complex values to the exchange.  FP32 also requests all
+// neighbours' records at once (n[2jj]: lane digit jj one step up, n[2jj+1]: one
+// step down), so their latencies overlap with the lane-independent work the caller
+// does before lane_digit_terms; FP64 (twice the registers per record) reads each
+// record only where it is used.
+template <typename T> struct XPre { static constexpr bool value = sizeof(T) == 4; };
 
 template <typename T, int Q, int L, int LD, int K>
-__device__ __forceinline__ void lane_digit_terms(const Lane<T, Q, L, LD> &ln, const T *lor, const T *loi,
-                                                 const T *hir, const T *hii, const T *vr, const T *vi, T *Sr,
-                                                 T *Si) {
+__device__ __forceinline__ void lane_exchange(const Lane<T, Q, L, LD> &ln, const T *vr, const T *vi,
+                                              T (*n)[2 * K]) {
   if constexpr (LD > 0) {
     T rec[2 * K];
 #pragma unroll
@@ -295,7 +299,31 @@ __device__ __forceinline__ void lane_digit_terms(const Lane<T, Q, L, LD> &ln, co
     }
     xput<T, 2 * K>(ln.xb, ln.lane, rec);
     wave_sync();
-    lane_digit_gets<T, Q, L, LD, K, 0>(ln, lor, loi, hir, hii, Sr, Si);
+    if constexpr (XPre<T>::value) {
+      LaneGets<T, LD, K, 0>::load(ln, n);
+      wave_sync();
+    }
+  }
+}
+
+template <typename T, int Q, int L, int LD, int K, int JJ = 0>
+__device__ __forceinline__ void lane_digit_terms(const Lane<T, Q, L, LD> &ln, const T *lor, const T *loi,
+                                                 const T *hir, const T *hii, T (*n)[2 * K], T *Sr, T *Si) {
+  if constexpr (JJ < LD) {
+    constexpr int ST = Geo<T, Q, L, LD>::lstride(JJ);
+    if constexpr (!XPre<T>::value) {
+      xget<T, 2 * K, ST>(ln.xb, ln.lane, n[0]);
+      xget<T, 2 * K, -ST>(ln.xb, ln.lane, n[1]);
+    }
+    const T *up = XPre<T>::value ? n[2 * JJ] : n[0];
+    const T *dn = XPre<T>::value ? n[2 * JJ + 1] : n[1];
+#pragma unroll
+    for (int o = 0; o < K; ++o) {
+      cmac(Sr[o], Si[o], lor[JJ], loi[JJ], up[2 * o], up[2 * o + 1]);
+      cmac(Sr[o], Si[o], hir[JJ], hii[JJ], dn[2 * o], dn[2 * o + 1]);
+    }
+    lane_digit_terms<T, Q, L, LD, K, JJ + 1>(ln, lor, loi, hir, hii, n, Sr, Si);
+  } else if constexpr (LD > 0 && !XPre<T>::value) {
     wave_sync();
   }
 }
@@ -307,6 +335,8 @@ __device__ __forceinline__ void apply_Hc(const Lane<T, Q, L, LD> &ln, const T *c
                                          const T *lor, const T *loi, const T *hir, const T *hii,
                                          const T *vr, const T *vi, T *Sr, T *Si) {
   using G = Geo<T, Q, L, LD>;
+  T n[2 * (LD > 0 ? LD : 1)][2 * G::EPL];
+  lane_exchange<T, Q, L, LD, G::EPL>(ln, vr, vi, n);
 #pragma unroll
   for (int e = 0; e < G::EPL; ++e) { Sr[e] = 0; Si[e] = 0; }
 #pragma unroll
@@ -325,7 +355,7 @@ __device__ __forceinline__ void apply_Hc(const Lane<T, Q, L, LD> &ln, const T *c
       }
     }
   }
-  lane_digit_terms<T, Q, L, LD, G::EPL>(ln, lor, loi, hir, hii, vr, vi, Sr, Si);
+  lane_digit_terms<T, Q, L, LD, G::EPL>(ln, lor, loi, hir, hii, n, Sr, Si);
 }
 
 // Per-step control coefficients: c'_j for register digits, per-lane lowering
@@ -396,6 +426,10 @@ __device__ __forceinline__ void apply_half(const Lane<T, Q, L, LD> &ln, const Co
                                            const T *vr, const T *vi, T *Sr, T *Si) {
   using G = Geo<T, Q, L, LD>;
   constexpr int IN = (1 - C) * G::H;
+  // lane digits: output slot o reads slot IN + o of the neighbouring lanes (the
+  // colour flips with the lane parity); requested first, used last
+  T n[2 * (LD > 0 ? LD : 1)][2 * G::H];
+  lane_exchange<T, Q, L, LD, G::H>(ln, vr + IN, vi + IN, n);
 #pragma unroll
   for (int t = 0; t < G::RT; ++t) {            // leading register digit
     const int beta = G::tpar(t) ^ C;
@@ -426,9 +460,7 @@ __device__ __forceinline__ void apply_half(const Lane<T, Q, L, LD> &ln, const Co
       }
     }
   }
-  // lane digits: output slot o reads slot IN + o of the neighbouring lanes (the
-  // colour flips with the lane parity)
-  lane_digit_terms<T, Q, L, LD, G::H>(ln, cf.lor, cf.loi, cf.hir, cf.hii, vr + IN, vi + IN, Sr, Si);
+  lane_digit_terms<T, Q, L, LD, G::H>(ln, cf.lor, cf.loi, cf.hir, cf.hii, n, Sr, Si);
 }
 
 __device__ __forceinline__ int kit_of(const DevSys &s) { return s.kit_fixed > 0 ? s.kit_fixed : *s.kit; }
@@ -541,15 +573,18 @@ __device__ __forceinline__ void forward_item(const DevSys &s, int m, int cg, dou
   const int kit = kit_of(s);
   const T *ctrl = reinterpret_cast<const T *>(s.ctrl);
   int next_boundary = 1;
+  int since = 0, icp = 0;              // steps since the last checkpoint, checkpoints written
 
   for (long long k = k0; k < k1; ++k) {
-    if (!ROLLOUT && s.ckpt_every > 0 && k > k0 && (k - k0) % s.ckpt_every == 0) {
-      const long long i = (k - k0) / s.ckpt_every - 1;
-      double2 *cp = reinterpret_cast<double2 *>(s.ckpt) + (((size_t)m * s.ncp + i) * s.E + ln.col) * s.N;
+    if (!ROLLOUT && s.ckpt_every > 0 && since == s.ckpt_every) {   // U_{k0 + (icp+1) C}
+      double2 *cp = reinterpret_cast<double2 *>(s.ckpt) + (((size_t)m * s.ncp + icp) * s.E + ln.col) * s.N;
       if (ln.valid)
 #pragma unroll
         for (int e = 0; e < G::EPL; ++e) cp[ln.row(e)] = double2{udr[e], udi[e]};
+      ++icp;
+      since = 0;
     }
+    ++since;
     Coef<T, Q, L, LD> cf;
     step_coeffs<T, Q, L, LD>(ln, ctrl, k, cf);
     T ur[G::EPL], ui[G::EPL], wr[G::EPL], wi[G::EPL];
@@ -805,6 +840,12 @@ __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T 
   const int kit = kit_of(s);
   const T *ctrl = reinterpret_cast<const T *>(s.ctrl);
   double *ser = s.series + (size_t)item * s.maxlen * 2 * Q;
+  // position of step k in its checkpoint interval: k - k0 = ic * C + jr
+  int jr = 0, ic = 0;
+  if (s.ckpt_every > 0) {
+    jr = (int)(k1 - 1 - k0) % s.ckpt_every;
+    ic = (int)(k1 - 1 - k0) / s.ckpt_every;
+  }
 
   for (long long k = k1 - 1; k >= k0; --k) {
     Coef<T, Q, L, LD> cf;
@@ -862,16 +903,24 @@ __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T 
       ldr[e] += 2.0 * (double)wlr[e];
       ldi[e] += 2.0 * (double)wli[e];
     }
-    if (s.ckpt_every > 0 && k > k0 && (k - k0) % s.ckpt_every == 0) {   // re-sync to the stored state
-      const long long i = (k - k0) / s.ckpt_every - 1;
-      const double2 *cp = reinterpret_cast<const double2 *>(s.ckpt) + (((size_t)m * s.ncp + i) * s.E + ln.col) * s.N;
-      if (ln.valid)
+    if (s.ckpt_every > 0) {
+      if (jr == 0 && ic > 0) {          // re-sync to the stored U_k, k - k0 = ic * C
+        const double2 *cp =
+            reinterpret_cast<const double2 *>(s.ckpt) + (((size_t)m * s.ncp + (ic - 1)) * s.E + ln.col) * s.N;
+        if (ln.valid)
 #pragma unroll
-        for (int e = 0; e < G::EPL; ++e) {
-          const double2 c = cp[ln.row(e)];
-          udr[e] = c.x;
-          udi[e] = c.y;
-        }
+          for (int e = 0; e < G::EPL; ++e) {
+            const double2 c = cp[ln.row(e)];
+            udr[e] = c.x;
+            udi[e] = c.y;
+          }
+      }
+      if (jr == 0) {
+        jr = s.ckpt_every - 1;
+        --ic;
+      } else {
+        --jr;
+      }
     }
   }
   if (!ln.valid) return;
