@@ -131,54 +131,54 @@ __device__ __forceinline__ void xchg_clear(T *buf) {
 }
 
 // v[0..NV) -> record of lane `lane`;  record of lane `lane + D` -> v[0..NV).
-// Records are accessed in 16-byte pieces when their size allows it (every piece
-// then stays 16-byte aligned), else in 8-byte pieces.
+// A record is split into planes of PW bytes (16 when the record size allows it,
+// else 8); plane p of all 64 + 2 kGuard lanes is contiguous, so the 64 lanes of
+// one access touch consecutive PW-byte words (no bank conflicts) and every access
+// stays PW-aligned.
 template <typename T, int NV>
 struct XRec {
   static_assert(NV <= kXchgMaxNV && (NV * sizeof(T)) % 8 == 0, "exchange record");
   static constexpr int BYTES = NV * (int)sizeof(T);
-  static constexpr bool WIDE = BYTES % 16 == 0;
+  static constexpr int PW = BYTES % 16 == 0 ? 16 : 8;          // plane width in bytes
+  static constexpr int PE = PW / (int)sizeof(T);               // values per plane
+  static constexpr int NP = BYTES / PW;                        // planes
+  static constexpr int PSTRIDE = (64 + 2 * kGuard) * PE;       // values between planes
 };
 
 template <typename T, int NV>
 __device__ __forceinline__ void xput(T *buf, int lane, const T *v) {
-  T *p = buf + (kGuard + lane) * NV;
-  if constexpr (sizeof(T) == 4) {
-    if constexpr (XRec<T, NV>::WIDE) {
+  using X = XRec<T, NV>;
+  T *p = buf + (kGuard + lane) * X::PE;
 #pragma unroll
-      for (int i = 0; i < NV; i += 4) *reinterpret_cast<float4 *>(p + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
-    } else {
-#pragma unroll
-      for (int i = 0; i < NV; i += 2) *reinterpret_cast<float2 *>(p + i) = make_float2(v[i], v[i + 1]);
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < NV; i += 2) *reinterpret_cast<double2 *>(p + i) = make_double2(v[i], v[i + 1]);
+  for (int q = 0; q < X::NP; ++q) {
+    const T *s = v + q * X::PE;
+    T *d = p + q * X::PSTRIDE;
+    if constexpr (X::PW == 16 && sizeof(T) == 4) *reinterpret_cast<float4 *>(d) = make_float4(s[0], s[1], s[2], s[3]);
+    else if constexpr (X::PW == 16) *reinterpret_cast<double2 *>(d) = make_double2(s[0], s[1]);
+    else if constexpr (sizeof(T) == 4) *reinterpret_cast<float2 *>(d) = make_float2(s[0], s[1]);
+    else d[0] = s[0];
   }
 }
 template <typename T, int NV, int D>
 __device__ __forceinline__ void xget(const T *buf, int lane, T *v) {
   static_assert(D >= -kGuard && D <= kGuard, "lane shift beyond the guard records");
-  const T *p = buf + (kGuard + lane + D) * NV;
-  if constexpr (sizeof(T) == 4) {
-    if constexpr (XRec<T, NV>::WIDE) {
+  using X = XRec<T, NV>;
+  const T *p = buf + (kGuard + lane + D) * X::PE;
 #pragma unroll
-      for (int i = 0; i < NV; i += 4) {
-        const float4 c = *reinterpret_cast<const float4 *>(p + i);
-        v[i] = c.x; v[i + 1] = c.y; v[i + 2] = c.z; v[i + 3] = c.w;
-      }
+  for (int q = 0; q < X::NP; ++q) {
+    T *d = v + q * X::PE;
+    const T *s = p + q * X::PSTRIDE;
+    if constexpr (X::PW == 16 && sizeof(T) == 4) {
+      const float4 c = *reinterpret_cast<const float4 *>(s);
+      d[0] = c.x; d[1] = c.y; d[2] = c.z; d[3] = c.w;
+    } else if constexpr (X::PW == 16) {
+      const double2 c = *reinterpret_cast<const double2 *>(s);
+      d[0] = c.x; d[1] = c.y;
+    } else if constexpr (sizeof(T) == 4) {
+      const float2 c = *reinterpret_cast<const float2 *>(s);
+      d[0] = c.x; d[1] = c.y;
     } else {
-#pragma unroll
-      for (int i = 0; i < NV; i += 2) {
-        const float2 c = *reinterpret_cast<const float2 *>(p + i);
-        v[i] = c.x; v[i + 1] = c.y;
-      }
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < NV; i += 2) {
-      const double2 c = *reinterpret_cast<const double2 *>(p + i);
-      v[i] = c.x; v[i + 1] = c.y;
+      d[0] = s[0];
     }
   }
 }
@@ -786,7 +786,8 @@ constexpr int red_elems() { return sizeof(T) == 4 ? 36 * 64 : 24 * 64; }   // 9 
 template <typename T, int Q>
 struct SeriesBuf {
   static constexpr int NV = 2 * Q;               // values per step
-  static constexpr int RS = 64 * NV + 8;         // elements per buffered step (padded)
+  static constexpr int VS = 65;                  // elements per (step, value) row: 64 lanes + 1 (bank offset)
+  static constexpr int RS = NV * VS;             // elements per buffered step
   static constexpr int RB = (red_elems<T>() / RS < 64 / NV) ? red_elems<T>() / RS : 64 / NV;   // steps per flush
   static_assert(RB >= 1, "reduction buffer too small");
 };
@@ -877,20 +878,20 @@ __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T 
     {
       using SB = SeriesBuf<T, Q>;
       const int idx = (int)(k - k0);
-      T *slot = red + (idx % SB::RB) * SB::RS + ln.lane * SB::NV;
+      T *slot = red + (idx % SB::RB) * SB::RS + ln.lane;
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
-        slot[2 * j] = s1[j];
-        slot[2 * j + 1] = s2[j];
+        slot[(2 * j) * SB::VS] = s1[j];
+        slot[(2 * j + 1) * SB::VS] = s2[j];
       }
       if (idx % SB::RB == 0) {             // steps idx .. idx+RB-1 are buffered: flush
         __syncthreads();
         const int r = ln.lane / SB::NV, vv = ln.lane % SB::NV;
         if (r < SB::RB && idx + r < (int)(k1 - k0)) {
-          const T *col = red + r * SB::RS + vv;
+          const T *col = red + r * SB::RS + vv * SB::VS;
           double acc = 0.0;
 #pragma unroll 8
-          for (int l = 0; l < 64; ++l) acc += (double)col[l * SB::NV];
+          for (int l = 0; l < 64; ++l) acc += (double)col[l];
           ser[(size_t)(idx + r) * SB::NV + vv] = acc;
         }
         __syncthreads();
