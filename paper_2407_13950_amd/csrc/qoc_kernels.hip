@@ -420,16 +420,13 @@ __device__ __forceinline__ void lead_operands(bool b, const T *xr, const T *xi, 
   pi[HALF] = xi[(HALF - 1) * stride];
 }
 
-// S = (dt/2) H_c v on the H slots of colour C, reading only the slots of colour 1-C.
+// Register-digit terms of S = (dt/2) H_c v on the H slots of colour C (S is
+// initialised here), reading only the slots of colour 1-C of v.
 template <typename T, int Q, int L, int LD, int C>
-__device__ __forceinline__ void apply_half(const Lane<T, Q, L, LD> &ln, const Coef<T, Q, L, LD> &cf,
-                                           const T *vr, const T *vi, T *Sr, T *Si) {
+__device__ __forceinline__ void apply_half_regs(const Lane<T, Q, L, LD> &ln, const Coef<T, Q, L, LD> &cf,
+                                                const T *vr, const T *vi, T *Sr, T *Si) {
   using G = Geo<T, Q, L, LD>;
   constexpr int IN = (1 - C) * G::H;
-  // lane digits: output slot o reads slot IN + o of the neighbouring lanes (the
-  // colour flips with the lane parity); requested first, used last
-  T n[2 * (LD > 0 ? LD : 1)][2 * G::H];
-  lane_exchange<T, Q, L, LD, G::H>(ln, vr + IN, vi + IN, n);
 #pragma unroll
   for (int t = 0; t < G::RT; ++t) {            // leading register digit
     const int beta = G::tpar(t) ^ C;
@@ -460,6 +457,19 @@ __device__ __forceinline__ void apply_half(const Lane<T, Q, L, LD> &ln, const Co
       }
     }
   }
+}
+
+// S = (dt/2) H_c v on the H slots of colour C, reading only the slots of colour 1-C.
+template <typename T, int Q, int L, int LD, int C>
+__device__ __forceinline__ void apply_half(const Lane<T, Q, L, LD> &ln, const Coef<T, Q, L, LD> &cf,
+                                           const T *vr, const T *vi, T *Sr, T *Si) {
+  using G = Geo<T, Q, L, LD>;
+  constexpr int IN = (1 - C) * G::H;
+  // lane digits: output slot o reads slot IN + o of the neighbouring lanes (the
+  // colour flips with the lane parity); requested first, used last
+  T n[2 * (LD > 0 ? LD : 1)][2 * G::H];
+  lane_exchange<T, Q, L, LD, G::H>(ln, vr + IN, vi + IN, n);
+  apply_half_regs<T, Q, L, LD, C>(ln, cf, vr, vi, Sr, Si);
   lane_digit_terms<T, Q, L, LD, G::H>(ln, cf.lor, cf.loi, cf.hir, cf.hii, n, Sr, Si);
 }
 
@@ -536,6 +546,72 @@ __device__ __forceinline__ void solve_increment(const Lane<T, Q, L, LD> &ln, int
 #pragma unroll
       for (int e = 0; e < G::EPL; ++e) jacobi_update<T, Q, L, LD, REV>(ln, e, Sr[e], Si[e], xr[e], xi[e], wr[e], wi[e]);
     }
+  }
+}
+
+// Half sweep of two right-hand sides with the same matrix (the backward sweep's
+// state and adjoint): their records travel in one exchange, so a step has half as
+// many LDS round trips.  Each result equals half_sweep on its own bit for bit.
+template <typename T, int Q, int L, int LD, bool REV, int C>
+__device__ __forceinline__ void half_sweep2(const Lane<T, Q, L, LD> &ln, const Coef<T, Q, L, LD> &cf,
+                                            const T *uar, const T *uai, const T *xar, const T *xai, T *war, T *wai,
+                                            const T *ubr, const T *ubi, const T *xbr, const T *xbi, T *wbr,
+                                            T *wbi) {
+  using G = Geo<T, Q, L, LD>;
+  constexpr int IN = (1 - C) * G::H, OUT = C * G::H;
+  T var[G::EPL], vai[G::EPL], vbr[G::EPL], vbi[G::EPL], rr[2 * G::H], ri[2 * G::H];
+#pragma unroll
+  for (int o = 0; o < G::H; ++o) {
+    var[IN + o] = uar[IN + o] + war[IN + o];
+    vai[IN + o] = uai[IN + o] + wai[IN + o];
+    vbr[IN + o] = ubr[IN + o] + wbr[IN + o];
+    vbi[IN + o] = ubi[IN + o] + wbi[IN + o];
+    rr[o] = var[IN + o];
+    ri[o] = vai[IN + o];
+    rr[G::H + o] = vbr[IN + o];
+    ri[G::H + o] = vbi[IN + o];
+  }
+  T n[2 * (LD > 0 ? LD : 1)][4 * G::H];
+  lane_exchange<T, Q, L, LD, 2 * G::H>(ln, rr, ri, n);
+  T Sr[2 * G::H], Si[2 * G::H];
+  apply_half_regs<T, Q, L, LD, C>(ln, cf, var, vai, Sr, Si);
+  apply_half_regs<T, Q, L, LD, C>(ln, cf, vbr, vbi, Sr + G::H, Si + G::H);
+  lane_digit_terms<T, Q, L, LD, 2 * G::H>(ln, cf.lor, cf.loi, cf.hir, cf.hii, n, Sr, Si);
+#pragma unroll
+  for (int o = 0; o < G::H; ++o) {
+    jacobi_update<T, Q, L, LD, REV>(ln, OUT + o, Sr[o], Si[o], xar[OUT + o], xai[OUT + o], war[OUT + o], wai[OUT + o]);
+    jacobi_update<T, Q, L, LD, REV>(ln, OUT + o, Sr[G::H + o], Si[G::H + o], xbr[OUT + o], xbi[OUT + o], wbr[OUT + o],
+                                    wbi[OUT + o]);
+  }
+}
+
+// Two right-hand sides with the same matrix; each result is bit-identical to
+// solve_increment on its own.
+template <typename T, int Q, int L, int LD, bool REV>
+__device__ __forceinline__ void solve_increment2(const Lane<T, Q, L, LD> &ln, int nit, const Coef<T, Q, L, LD> &cf,
+                                                 const T *ar, const T *ai, T *war, T *wai,
+                                                 const T *br, const T *bi, T *wbr, T *wbi) {
+  using G = Geo<T, Q, L, LD>;
+  if constexpr (G::RB) {
+    T xar[G::EPL], xai[G::EPL], xbr[G::EPL], xbi[G::EPL];
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {
+      ln.template scale_m1<REV>(e, ar[e], ai[e], xar[e], xai[e]);
+      ln.template scale_m1<REV>(e, br[e], bi[e], xbr[e], xbi[e]);
+      war[e] = xar[e];
+      wai[e] = xai[e];
+      wbr[e] = xbr[e];
+      wbi[e] = xbi[e];
+    }
+    int h = 0;
+    for (; h + 1 < nit; h += 2) {
+      half_sweep2<T, Q, L, LD, REV, 0>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+      half_sweep2<T, Q, L, LD, REV, 1>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+    }
+    if (h < nit) half_sweep2<T, Q, L, LD, REV, 0>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+  } else {
+    solve_increment<T, Q, L, LD, REV>(ln, nit, cf, ar, ai, war, wai);
+    solve_increment<T, Q, L, LD, REV>(ln, nit, cf, br, bi, wbr, wbi);
   }
 }
 
@@ -860,8 +936,7 @@ __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T 
       lr[e] = (T)ldr[e];
       li[e] = (T)ldi[e];
     }
-    solve_increment<T, Q, L, LD, true>(ln, kit, cf, ur, ui, wur, wui);
-    solve_increment<T, Q, L, LD, true>(ln, kit, cf, lr, li, wlr, wli);
+    solve_increment2<T, Q, L, LD, true>(ln, kit, cf, ur, ui, wur, wui, lr, li, wlr, wli);
     T zr[G::EPL], zi[G::EPL], yr[G::EPL], yi[G::EPL];
 #pragma unroll
     for (int e = 0; e < G::EPL; ++e) {
