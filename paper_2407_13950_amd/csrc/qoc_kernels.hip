@@ -400,6 +400,16 @@ __device__ __forceinline__ void step_coeffs(const Lane<T, Q, L, LD> &ln, const T
   }
 }
 
+// Pair terms of the per-step inner products for rows e (digit l) and f (digit l+1):
+// a1 = Im(conj(y_e) z_f + conj(y_f) z_e), a2 = Re(conj(y_e) z_f - conj(y_f) z_e).
+template <typename T>
+__device__ __forceinline__ void pair_terms(T yer, T yei, T zer, T zei, T yfr, T yfi, T zfr, T zfi, T &a1, T &a2) {
+  a1 = yer * zfi;
+  a2 = yer * zfr;
+  a1 = fma_(-yei, zfr, a1); a1 = fma_(yfr, zei, a1); a1 = fma_(-yfi, zer, a1);
+  a2 = fma_(yei, zfi, a2); a2 = fma_(-yfr, zer, a2); a2 = fma_(-yfi, zei, a2);
+}
+
 // ---------------------------------------------------------------------------- red-black half sweep
 
 // Operands of the leading register digit for the output slots (s0, t) of one colour:
@@ -549,14 +559,58 @@ __device__ __forceinline__ void solve_increment(const Lane<T, Q, L, LD> &ln, int
   }
 }
 
+// Lane-digit inner-product terms of the last half sweep.  After it, the slots of
+// colour C (updated last) and the neighbours' slots of colour 1-C (records n) are
+// final; every pair of rows one lane digit apart has exactly one row of colour C,
+// so pairing each own slot with its upper neighbour (weight sqrt(l+1)) and its
+// lower neighbour (weight sqrt(l)) visits every pair once.  a1 = Im(conj(y) z' +
+// conj(y') z) is symmetric in the pair and a2 = Re(conj(y_lo) z_hi - conj(y_hi) z_lo)
+// changes sign with it.
+template <typename T, int Q, int L, int LD, int K, int JJ = 0>
+__device__ __forceinline__ void last_inner_lane(const Lane<T, Q, L, LD> &ln, T (*n)[4 * K], const T *zr, const T *zi,
+                                                const T *yr, const T *yi, T *s1, T *s2) {
+  using G = Geo<T, Q, L, LD>;
+  if constexpr (JJ < LD) {
+    constexpr int ST = G::lstride(JJ);
+    T up[4 * K], dn[4 * K];
+    if constexpr (XPre<T>::value) {
+#pragma unroll
+      for (int i = 0; i < 4 * K; ++i) {
+        up[i] = n[2 * JJ][i];
+        dn[i] = n[2 * JJ + 1][i];
+      }
+    } else {
+      xget<T, 4 * K, ST>(ln.xb, ln.lane, up);
+      xget<T, 4 * K, -ST>(ln.xb, ln.lane, dn);
+    }
+    T u1 = 0, u2 = 0, d1 = 0, d2 = 0;
+#pragma unroll
+    for (int o = 0; o < K; ++o) {      // record: K complex z values, then K complex y values
+      T a1, a2;
+      pair_terms(yr[o], yi[o], zr[o], zi[o], up[2 * K + 2 * o], up[2 * K + 2 * o + 1], up[2 * o], up[2 * o + 1], a1, a2);
+      u1 += a1;
+      u2 += a2;
+      pair_terms(yr[o], yi[o], zr[o], zi[o], dn[2 * K + 2 * o], dn[2 * K + 2 * o + 1], dn[2 * o], dn[2 * o + 1], a1, a2);
+      d1 += a1;
+      d2 += a2;
+    }
+    s1[G::R + JJ] = fma_(ln.whi[JJ], d1, ln.wlo[JJ] * u1);
+    s2[G::R + JJ] = fma_(-ln.whi[JJ], d2, ln.wlo[JJ] * u2);
+    last_inner_lane<T, Q, L, LD, K, JJ + 1>(ln, n, zr, zi, yr, yi, s1, s2);
+  } else if constexpr (LD > 0 && !XPre<T>::value) {
+    wave_sync();
+  }
+}
+
 // Half sweep of two right-hand sides with the same matrix (the backward sweep's
 // state and adjoint): their records travel in one exchange, so a step has half as
 // many LDS round trips.  Each result equals half_sweep on its own bit for bit.
-template <typename T, int Q, int L, int LD, bool REV, int C>
+// LAST: also the lane-digit inner products of the final z and y (last_inner_lane).
+template <typename T, int Q, int L, int LD, bool REV, int C, bool LAST = false>
 __device__ __forceinline__ void half_sweep2(const Lane<T, Q, L, LD> &ln, const Coef<T, Q, L, LD> &cf,
                                             const T *uar, const T *uai, const T *xar, const T *xai, T *war, T *wai,
                                             const T *ubr, const T *ubi, const T *xbr, const T *xbi, T *wbr,
-                                            T *wbi) {
+                                            T *wbi, T *s1 = nullptr, T *s2 = nullptr) {
   using G = Geo<T, Q, L, LD>;
   constexpr int IN = (1 - C) * G::H, OUT = C * G::H;
   T var[G::EPL], vai[G::EPL], vbr[G::EPL], vbi[G::EPL], rr[2 * G::H], ri[2 * G::H];
@@ -583,14 +637,32 @@ __device__ __forceinline__ void half_sweep2(const Lane<T, Q, L, LD> &ln, const C
     jacobi_update<T, Q, L, LD, REV>(ln, OUT + o, Sr[G::H + o], Si[G::H + o], xbr[OUT + o], xbi[OUT + o], wbr[OUT + o],
                                     wbi[OUT + o]);
   }
+  if constexpr (LAST) {
+    T zr[G::H], zi[G::H], yr[G::H], yi[G::H];
+#pragma unroll
+    for (int o = 0; o < G::H; ++o) {
+      zr[o] = uar[OUT + o] + war[OUT + o];
+      zi[o] = uai[OUT + o] + wai[OUT + o];
+      yr[o] = ubr[OUT + o] + wbr[OUT + o];
+      yi[o] = ubi[OUT + o] + wbi[OUT + o];
+    }
+    last_inner_lane<T, Q, L, LD, G::H>(ln, n, zr, zi, yr, yi, s1, s2);
+  }
 }
 
-// Two right-hand sides with the same matrix; each result is bit-identical to
-// solve_increment on its own.
+// Lane-digit inner products taken inside the last half sweep: red-black layout in
+// FP32 (FP64 lacks the registers to keep the records, it exchanges z and y again).
+template <typename T, int L>
+constexpr bool fused_inner() { return (L % 2) == 0 && XPre<T>::value; }
+
+// Two right-hand sides with the same matrix (a: state, b: adjoint); each result is
+// bit-identical to solve_increment on its own.  When fused_inner, the lane-digit
+// inner products of the solutions are left in s1, s2 (entries R..q-1), taken in
+// the last half sweep; nit >= 1.
 template <typename T, int Q, int L, int LD, bool REV>
 __device__ __forceinline__ void solve_increment2(const Lane<T, Q, L, LD> &ln, int nit, const Coef<T, Q, L, LD> &cf,
                                                  const T *ar, const T *ai, T *war, T *wai,
-                                                 const T *br, const T *bi, T *wbr, T *wbi) {
+                                                 const T *br, const T *bi, T *wbr, T *wbi, T *s1, T *s2) {
   using G = Geo<T, Q, L, LD>;
   if constexpr (G::RB) {
     T xar[G::EPL], xai[G::EPL], xbr[G::EPL], xbi[G::EPL];
@@ -604,11 +676,24 @@ __device__ __forceinline__ void solve_increment2(const Lane<T, Q, L, LD> &ln, in
       wbi[e] = xbi[e];
     }
     int h = 0;
-    for (; h + 1 < nit; h += 2) {
-      half_sweep2<T, Q, L, LD, REV, 0>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
-      half_sweep2<T, Q, L, LD, REV, 1>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+    if constexpr (fused_inner<T, L>()) {
+      for (; h + 2 < nit; h += 2) {
+        half_sweep2<T, Q, L, LD, REV, 0>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+        half_sweep2<T, Q, L, LD, REV, 1>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+      }
+      if (nit - h == 2) {
+        half_sweep2<T, Q, L, LD, REV, 0>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+        half_sweep2<T, Q, L, LD, REV, 1, true>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi, s1, s2);
+      } else {
+        half_sweep2<T, Q, L, LD, REV, 0, true>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi, s1, s2);
+      }
+    } else {
+      for (; h + 1 < nit; h += 2) {
+        half_sweep2<T, Q, L, LD, REV, 0>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+        half_sweep2<T, Q, L, LD, REV, 1>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+      }
+      if (h < nit) half_sweep2<T, Q, L, LD, REV, 0>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
     }
-    if (h < nit) half_sweep2<T, Q, L, LD, REV, 0>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
   } else {
     solve_increment<T, Q, L, LD, REV>(ln, nit, cf, ar, ai, war, wai);
     solve_increment<T, Q, L, LD, REV>(ln, nit, cf, br, bi, wbr, wbi);
@@ -708,16 +793,6 @@ template <typename G>
 __device__ __forceinline__ constexpr int partner(int e) {
   if constexpr (G::RB) return e < G::H ? e + G::H : e - G::H;
   else return e;
-}
-
-// Pair terms of the per-step inner products for rows e (digit l) and f (digit l+1):
-// a1 = Im(conj(y_e) z_f + conj(y_f) z_e), a2 = Re(conj(y_e) z_f - conj(y_f) z_e).
-template <typename T>
-__device__ __forceinline__ void pair_terms(T yer, T yei, T zer, T zei, T yfr, T yfi, T zfr, T zfi, T &a1, T &a2) {
-  a1 = yer * zfi;
-  a2 = yer * zfr;
-  a1 = fma_(-yei, zfr, a1); a1 = fma_(yfr, zei, a1); a1 = fma_(-yfi, zer, a1);
-  a2 = fma_(yei, zfi, a2); a2 = fma_(-yfr, zer, a2); a2 = fma_(-yfi, zei, a2);
 }
 
 // Register-digit part of the per-step inner products (see backward_item).
@@ -936,7 +1011,8 @@ __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T 
       lr[e] = (T)ldr[e];
       li[e] = (T)ldi[e];
     }
-    solve_increment2<T, Q, L, LD, true>(ln, kit, cf, ur, ui, wur, wui, lr, li, wlr, wli);
+    T s1[Q], s2[Q];
+    solve_increment2<T, Q, L, LD, true>(ln, kit, cf, ur, ui, wur, wui, lr, li, wlr, wli, s1, s2);
     T zr[G::EPL], zi[G::EPL], yr[G::EPL], yi[G::EPL];
 #pragma unroll
     for (int e = 0; e < G::EPL; ++e) {
@@ -947,9 +1023,8 @@ __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T 
     }
     // inner products per qubit: s1 = Im(A + B), s2 = Re(A - B) with
     // A = <y, a_j z> = sum conj(y_r) sqrt(l+1) z_{r+st},  B = <y, a_j^+ z> = sum sqrt(l+1) conj(y_{r+st}) z_r
-    T s1[Q], s2[Q];
     inner_register_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
-    inner_lane_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
+    if constexpr (!fused_inner<T, L>()) inner_lane_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
     {
       using SB = SeriesBuf<T, Q>;
       const int idx = (int)(k - k0);
