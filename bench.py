@@ -22,8 +22,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_VECTOR_TFLOPS = 157.3      # MI355X published FP32 vector peak (packed)
-PEAK_FP32_NONPACKED_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (packed FP32 is not used)
+PEAK_FP32_VECTOR_TFLOPS = 157.3      # MI355X published FP32 vector peak (plain FP32 FMAs reach it: two per SIMD per 4 clocks)
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
@@ -173,8 +172,9 @@ def bench_serve(rate, n_requests, plain_requests, seed, budget_gb, log):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=30)
+    # the sweeps run about 20% slow for the first ~10 evaluations while the GPU clocks ramp up
+    ap.add_argument("--warmup", type=int, default=15)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=3, help="steps of the plain FP64 form timed for comparison")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU-oracle sample size (0: skip)")
@@ -280,7 +280,6 @@ def main():
                      "unit": "TFLOP/s",
                      "frac": achieved / (PEAK_FP32_VECTOR_TFLOPS if args.precision == "fp32" else PEAK_FP64_VECTOR_TFLOPS),
                      "traffic": measured_traffic(kname),
-                     "peak_without_packed_fp32": PEAK_FP32_NONPACKED_TFLOPS,
                      "flops_per_launch": flops, "mean_launch_ms": tm[dominant]},
         "P": float(P.item()),
     }

@@ -21,9 +21,9 @@
 // (qubit 0 most significant) split into "register digits" (the leading q-LD,
 // encoded in e) and "lane digits" (the trailing LD, encoded in sub).  A ladder
 // operator on a register digit reads another register of the same lane (no data
-// movement); on a lane digit it reads the same register of the lane +-L^k away
-// (cross-lane permute).  A wavefront holds CPW = 64/pow2ceil(LPC) columns of one
-// window, so all its lanes see the same control values at every step.
+// movement); on a lane digit it reads the lane +-L^k away, through a per-wavefront
+// LDS exchange (see lane exchange).  A wavefront holds CPW = 64/pow2ceil(LPC)
+// columns of one window, so all its lanes see the same control values at every step.
 //
 // One fixed-point (Jacobi) iteration for (I + i dt/2 H) z = u with the diagonal
 // drift D = I + i dt/2 diag(h) split off:  z <- D^{-1} (u - i S), S = (dt/2) H_c z.
