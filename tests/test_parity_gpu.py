@@ -170,3 +170,34 @@ def test_fixed_iteration_override_and_convergence_flag():
     P, _ = s.objective()
     P0, _ = O.objective(w, alpha, W)
     assert abs(P - P0) <= 1e-12 * abs(P0)
+
+
+@pytest.mark.parametrize("q,L,prec,counts", [
+    (4, 4, "fp32", (5, 6, 9)),     # red-black: the last half sweep is red for odd counts, black for even
+    (3, 4, "fp32", (5,)),
+    (3, 2, "fp32", (5, 6)),
+    (4, 4, "fp64", (7, 8)),
+    (2, 3, "fp32", (4, 5)),        # odd L: Jacobi iterations
+])
+def test_forced_counts_match_oracle(q, L, prec, counts):
+    """Caller-forced fixed-point counts of both parities.  In the red-black solve the lane-digit
+    inner products of the backward sweep are taken in whichever half sweep comes last, so both
+    colours must serve as the last one."""
+    w, alpha, W = small_case(q, L, 200, 4)
+    P0, t0, ga0, gW0 = O.gradient(w, alpha, W)
+    g0 = np.concatenate([ga0, gW0.view(np.float64).ravel()])
+    tol_P, tol_g = (1e-11, 1e-10) if prec == "fp64" else (1e-5, 1e-4)
+    for n in counts:
+        P, t, ga, gW = run_gpu(w, alpha, W, prec, fixed_point_iters=n)
+        g = rel(np.concatenate([ga, gW.view(np.float64).ravel()]), g0)
+        print(f"{w.name} {prec} count {n}: P rel {abs(P - P0) / abs(P0):.2e}  grad rel-L2 {g:.2e}", flush=True)
+        assert abs(P - P0) <= tol_P * abs(P0) and g <= tol_g
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_minimal_forced_counts_run(n):
+    """One to three half sweeps at 4 qubits: a truncated solve (no accuracy claim), but every
+    tail of the red-black loop runs and returns finite values."""
+    w, alpha, W = small_case(4, 4, 60, 3)
+    P, t, ga, gW = run_gpu(w, alpha, W, "fp32", fixed_point_iters=n)
+    assert np.isfinite(P) and np.all(np.isfinite(ga)) and np.all(np.isfinite(gW.view(np.float64)))
