@@ -200,6 +200,70 @@ typedef struct qoc_timings {
 int qoc_enable_timing(qoc_ctx *ctx, int32_t on);
 int qoc_get_timings(qoc_ctx *ctx, qoc_timings *out);
 
+/* ---- Optimisation driver: the quadratic-penalty method of Sec. 3 with the
+ * settings of Sec. 5 (L-BFGS, box constraints, Tikhonov and energy terms, scaled
+ * window states, roll-out-estimate stopping rule), run over the calls above.
+ *
+ * Variables x = [alpha (d doubles), sigma * W (2*(M-1)*N*E doubles, layout of W)]
+ * (W scaled by sigma as in Sec. 5).  The driver minimises
+ *   F(x) = P(alpha, W) + gamma_tik/2 |alpha|^2 + gamma_energy * Ee(alpha),
+ *   Ee(alpha) = dt * sum_k sum_j |d_j(t_{k+1/2})|^2   (GHz^2 ns, d_j as in eq. dj-ctrl),
+ * subject to |alpha_i| <= amp_bound / (sqrt(2) * n_carriers): then
+ * |d_j(t)| <= amp_bound for all t (the B-splines sum to one).
+ * Iteration (both sides of the parity tests implement exactly this):
+ *   active set: alpha_i at a bound with the gradient pointing outwards;
+ *   gr = gradient with active entries zeroed;
+ *   p = -H gr by the L-BFGS two-loop recursion over the last `memory` pairs
+ *     (s, y) with H0 = (s.y / y.y) I of the newest pair; active entries of p
+ *     zeroed; p = -gr when the history is empty or p is not a descent direction
+ *     (the history is then cleared);
+ *   backtracking from t0 = 1 (t0 = 1 / max(1, |gr|_2) without history), halving
+ *     up to 30 times: x_t = clip(x + t p), accepted when
+ *     F(x_t) <= F(x) + 1e-4 * g.(x_t - x);
+ *   the pair (s, y) = (x_t - x, g_t - g) is kept when s.y > 1e-12 |s| |y|.
+ * Stops when the roll-out infidelity estimate (eq. rollout-infid-est, with
+ * n = E) of the current iterate is below tol_estimate, when |gr|_inf <
+ * tol_grad, or when no step is accepted.  Trial points cost one objective
+ * evaluation; an accepted point adds one adjoint sweep (qoc_backward).  All
+ * vectors live in device memory of the context's device. */
+typedef struct qoc_opt qoc_opt;
+typedef struct qoc_opt_desc {
+  double sigma;                 /* window-state scale, > 0 (Sec. 5: 0.05 .. 0.15)    */
+  double gamma_tik;             /* Tikhonov coefficient, >= 0 (Sec. 5: 1e-3 / d)     */
+  double gamma_energy;          /* energy coefficient, >= 0 (Sec. 5: 1e-3)           */
+  double amp_bound;             /* pulse amplitude bound in GHz, > 0 (Sec. 5: 0.025) */
+  int32_t memory;               /* L-BFGS pairs kept, 1..64                          */
+  double tol_estimate;          /* stop below this roll-out estimate (Sec. 5: 1e-3)  */
+  double tol_grad;              /* stop below this |gr|_inf (0: never)               */
+} qoc_opt_desc;
+
+typedef struct qoc_opt_status {
+  int32_t iterations;           /* accepted steps so far                             */
+  int32_t evaluations;          /* objective evaluations (trial points)              */
+  int32_t backward_sweeps;      /* adjoint sweeps                                    */
+  int32_t stop;                 /* 0 running, 1 estimate below tol, 2 gradient below
+                                   tol, 3 no step accepted                           */
+  double F, P, J, penalty, energy, tikhonov;   /* at the current iterate             */
+  double estimate;              /* roll-out infidelity estimate at the iterate       */
+  double grad_inf;              /* |gr|_inf at the iterate                           */
+  double last_step;             /* accepted step length t of the last iteration      */
+} qoc_opt_status;
+
+/* Start an optimisation on ctx (which then belongs to it until qoc_opt_destroy;
+ * the context's stream is used).  alpha0: d doubles (clipped to the box); W0:
+ * 2*(M-1)*N*E doubles, unscaled (Sec. 5 starts from the roll-out states;
+ * NULL = roll out alpha0 on the GPU); both on `where`.  Evaluates F and its
+ * gradient at the start point.  Errors: QOC_EINVAL, QOC_ENOMEM, QOC_ENOTCONV. */
+int qoc_opt_create(qoc_ctx *ctx, const qoc_opt_desc *desc, const double *alpha0, const double *W0, int32_t where,
+                   qoc_opt **out);
+int qoc_opt_destroy(qoc_opt *opt);
+/* Up to n_iters iterations (fewer when a stop condition holds); status
+ * (nullable) describes the current iterate afterwards. */
+int qoc_opt_run(qoc_opt *opt, int32_t n_iters, qoc_opt_status *status);
+/* The current iterate: alpha (d doubles) and W (unscaled, 2*(M-1)*N*E doubles);
+ * both nullable, on `where`. */
+int qoc_opt_get(qoc_opt *opt, double *alpha, double *W, int32_t where);
+
 /* Block until this context's queued work is done; returns QOC_ENOTCONV if a
  * previous evaluation flagged a fixed-point bound violation (then clears it). */
 int qoc_synchronize(qoc_ctx *ctx);

@@ -70,6 +70,7 @@ def _load():
                 "orc_apply_H": [P, vp, dbl, i, vp, vp],
                 "orc_propagate": [P, vp, l, l, i, i, vp],
                 "orc_infidelity": [P, vp, vp],
+                "orc_energy": [P, vp, vp, vp],
                 "orc_window_starts": [P, vp],
             }
             for name, args in sig.items():
@@ -233,6 +234,16 @@ def infidelity(w, U) -> float:
     J = np.zeros(1)
     _check(_load().orc_infidelity(pb.ref(), U.ctypes.data, J.ctypes.data), "infidelity")
     return float(J[0])
+
+
+def energy(w, alpha, grad: bool = True):
+    """Control energy Ee(alpha) = dt sum_k sum_j |d_j(t_{k+1/2})|^2 (GHz^2 ns) and its gradient [d]."""
+    pb = Problem(w)
+    E = np.zeros(1)
+    g = np.zeros(w.d) if grad else None
+    _check(_load().orc_energy(pb.ref(), _c(alpha, np.float64).ctypes.data, E.ctypes.data,
+                              g.ctypes.data if grad else None), "energy")
+    return (float(E[0]), g) if grad else float(E[0])
 
 
 def window_starts(w) -> np.ndarray:

@@ -633,3 +633,39 @@ int orc_window_starts(const orc_problem *p, long *starts)
     for (int m = 1; m <= p->M + 1; ++m) starts[m - 1] = window_start(p, m);
     return ORC_OK;
 }
+
+/* Control energy of the optimisation settings (Sec. 5, energy penalty integral):
+ *   Ee(alpha) = dt sum_{k=0}^{N_T-1} sum_j |d_j(t_{k+1/2})|^2,   d_j = c_j / (2 pi) in GHz,
+ * the midpoint rule on the propagation grid, and its exact gradient
+ *   dEe/dalpha_l = 2 dt sum_k sum_j Re(conj(d_j) dd_j/dalpha_l),
+ * dd_j/da1_jfs = B_s(t) e^{i W_jf t}, dd_j/da2_jfs = i B_s(t) e^{i W_jf t}.  grad may be NULL. */
+int orc_energy(const orc_problem *p, const double *alpha, double *E_out, double *grad)
+{
+    const double dt = p->T / (double)p->n_steps;
+    const int d = p->q * p->nf * 2 * p->d1;
+    cplx c[64];
+    if (p->q > 64) return ORC_EINVAL;
+    if (grad) memset(grad, 0, sizeof(double) * d);
+    double E = 0.0;
+    for (long k = 0; k < p->n_steps; ++k) {
+        const double t = (k + 0.5) * dt;
+        controls(p, alpha, t, c);
+        for (int j = 0; j < p->q; ++j) {
+            const cplx dj = c[j] / (2.0 * M_PI);
+            E += creal(dj) * creal(dj) + cimag(dj) * cimag(dj);
+            if (!grad) continue;
+            for (int f = 0; f < p->nf; ++f) {
+                const double om = p->carrier[j * p->nf + f];
+                const cplx ph = cexp(I * om * t);
+                for (int s = 0; s < p->d1; ++s) {
+                    const double b = spline_value(p, s, t);
+                    if (b == 0.0) continue;
+                    grad[alpha_index(p, j, f, 0, s)] += 2.0 * dt * creal(conj(dj) * b * ph);
+                    grad[alpha_index(p, j, f, 1, s)] += 2.0 * dt * creal(conj(dj) * I * b * ph);
+                }
+            }
+        }
+    }
+    *E_out = dt * E;
+    return ORC_OK;
+}

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqoc.so")
-SOURCES = ["qoc_kernels.hip", "qoc_api.cpp"]
+SOURCES = ["qoc_kernels.hip", "qoc_opt_kernels.hip", "qoc_api.cpp", "qoc_opt.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are switched off for all device code.

@@ -97,6 +97,13 @@ struct qoc_ctx {
   hipEvent_t ev(int call, int k) { return events[(size_t)call * (qoc::N_PHASES + 1) + k]; }
 };
 
+namespace qoc {
+const DevSys &ctx_dev(const qoc_ctx *ctx) { return ctx->dev; }
+hipStream_t ctx_stream(const qoc_ctx *ctx) { return ctx->stream; }
+int ctx_device(const qoc_ctx *ctx) { return ctx->device; }
+int set_error(int code, const char *msg) { return fail(code, msg); }
+}  // namespace qoc
+
 extern "C" {
 
 const char *qoc_last_error(void) { return g_last_error.c_str(); }

@@ -82,4 +82,31 @@ struct BatchPlan {
 };
 int launch_batch_phase(const BatchPlan &p, int phase, hipStream_t st);
 
+// ---- optimisation driver (qoc_opt.cpp) and its FP64 kernels (qoc_opt_kernels.hip).
+// Reductions use kOptGrid partial sums (partials: >= kOptGrid doubles) finished by one
+// block in a fixed order; results land in device memory.  All return 0 or a hipError_t.
+constexpr int kOptGrid = 512;
+int opt_dot(const double *a, const double *b, long long n, double *partials, double *out, hipStream_t st);
+int opt_maxabs(const double *v, long long n, double *partials, double *out, hipStream_t st);
+int opt_axpby(double *y, double a, const double *x, double b, long long n, hipStream_t st);       // y = a x + b y
+int opt_trial(double *xt, const double *x, const double *p, double t, long long n, long long d, double lo, double hi,
+              hipStream_t st);                                                                       // clip(x + t p)
+int opt_reduced(double *out, const double *v, const double *x, const double *g, long long n, long long d, double lo,
+                double hi, hipStream_t st);                                                          // v off the active set
+int opt_assemble(double *g, const double *ga, const double *alpha, const double *gE, const double *gW, long long d,
+                 long long nW, double gtik, double gen, double s, hipStream_t st);
+int opt_energy_blocks(const DevSys &s);                 // partials needed by opt_energy
+// sum_k sum_j |d_j(t_{k+1/2})|^2 -> out; d_j per step -> dtab [2*NT*q]
+int opt_energy(const DevSys &s, const double *alpha, double *dtab, double *partials, double *out, hipStream_t st);
+int opt_energy_grad(const DevSys &s, const double *dtab, double *gE, hipStream_t st);
+
+}  // namespace qoc
+
+// Host-side views of a context for the optimisation driver (defined in qoc_api.cpp).
+struct qoc_ctx;
+namespace qoc {
+const DevSys &ctx_dev(const qoc_ctx *ctx);
+hipStream_t ctx_stream(const qoc_ctx *ctx);
+int ctx_device(const qoc_ctx *ctx);
+int set_error(int code, const char *msg);      // records the message for qoc_last_error, returns code
 }  // namespace qoc

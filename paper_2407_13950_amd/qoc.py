@@ -31,7 +31,8 @@ QOC_FP64, QOC_FP32 = 0, 1
 EXPORTED = ["qoc_create", "qoc_destroy", "qoc_get_info", "qoc_set_stream", "qoc_set_controls",
             "qoc_set_window_states", "qoc_objective", "qoc_gradient", "qoc_rollout", "qoc_synchronize",
             "qoc_last_error", "qoc_strerror", "qoc_enable_timing", "qoc_get_timings", "qoc_backward",
-            "qoc_batch_create", "qoc_batch_destroy", "qoc_batch_run", "qoc_read_results"]
+            "qoc_batch_create", "qoc_batch_destroy", "qoc_batch_run", "qoc_read_results",
+            "qoc_opt_create", "qoc_opt_destroy", "qoc_opt_run", "qoc_opt_get"]
 
 PHASES = ["controls", "forward", "boundary", "backward", "project", "grad_W", "total"]
 
@@ -63,6 +64,19 @@ class Info(ctypes.Structure):
 class Timings(ctypes.Structure):
     _fields_ = [("n_calls", ctypes.c_int32), ("n_grad_calls", ctypes.c_int32), ("mean_ms", ctypes.c_double * 8),
                 ("fixed_point_iters", ctypes.c_int32)]
+
+
+class OptDesc(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_double), ("gamma_tik", ctypes.c_double), ("gamma_energy", ctypes.c_double),
+                ("amp_bound", ctypes.c_double), ("memory", ctypes.c_int32), ("tol_estimate", ctypes.c_double),
+                ("tol_grad", ctypes.c_double)]
+
+
+class OptStatus(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("evaluations", ctypes.c_int32), ("backward_sweeps", ctypes.c_int32),
+                ("stop", ctypes.c_int32), ("F", ctypes.c_double), ("P", ctypes.c_double), ("J", ctypes.c_double),
+                ("penalty", ctypes.c_double), ("energy", ctypes.c_double), ("tikhonov", ctypes.c_double),
+                ("estimate", ctypes.c_double), ("grad_inf", ctypes.c_double), ("last_step", ctypes.c_double)]
 
 
 _lib = None
@@ -97,6 +111,10 @@ def load_library(path: str = LIB_PATH):
         "qoc_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "qoc_enable_timing": ([vp, i32], ctypes.c_int),
         "qoc_get_timings": ([vp, ctypes.POINTER(Timings)], ctypes.c_int),
+        "qoc_opt_create": ([vp, ctypes.POINTER(OptDesc), vp, vp, i32, ctypes.POINTER(vp)], ctypes.c_int),
+        "qoc_opt_destroy": ([vp], ctypes.c_int),
+        "qoc_opt_run": ([vp, i32, ctypes.POINTER(OptStatus)], ctypes.c_int),
+        "qoc_opt_get": ([vp, vp, vp, i32], ctypes.c_int),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -318,3 +336,60 @@ class Batch:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
         _check(_lib.qoc_batch_run(self.h, arr, n, wg, ctypes.c_void_p(stream)))
+
+
+STOP_REASONS = {0: "running", 1: "estimate", 2: "gradient", 3: "line search"}
+
+
+class Optimizer:
+    """Quadratic-penalty L-BFGS over a System (qoc_opt_*; iteration as specified in include/qoc.h).
+
+    Defaults follow Sec. 5: sigma 0.1 (of the scanned 0.05..0.15), gamma_tik 1e-3/d, gamma_energy 1e-3,
+    pulse amplitude bound 25 MHz, stop at a roll-out estimate of 1e-3.  W0=None starts from the
+    roll-out of alpha0 (computed on the GPU).  The System belongs to the optimiser until close()."""
+
+    def __init__(self, system: System, alpha0, W0=None, sigma: float = 0.1, gamma_tik: Optional[float] = None,
+                 gamma_energy: float = 1e-3, amp_bound: float = 0.025, memory: int = 10,
+                 tol_estimate: float = 1e-3, tol_grad: float = 0.0):
+        lib = load_library()
+        self.system = system
+        self.desc = OptDesc(sigma, (1e-3 / system.d) if gamma_tik is None else gamma_tik, gamma_energy, amp_bound,
+                            memory, tol_estimate, tol_grad)
+        a = np.ascontiguousarray(alpha0, dtype=np.float64)
+        Wp = None
+        if W0 is not None and system.M > 1:
+            Wk = np.ascontiguousarray(W0, dtype=np.complex128)
+            if Wk.shape != (system.M - 1, system.E, system.N):
+                raise ValueError(f"W0 must have shape {(system.M - 1, system.E, system.N)}")
+            self._W0 = Wk
+            Wp = Wk.ctypes.data
+        h = ctypes.c_void_p()
+        _check(lib.qoc_opt_create(system.h, ctypes.byref(self.desc), a.ctypes.data, Wp, QOC_HOST, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            _lib.qoc_opt_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, n_iters: int) -> dict:
+        """Up to n_iters iterations; returns the status of the current iterate."""
+        st = OptStatus()
+        _check(_lib.qoc_opt_run(self.h, n_iters, ctypes.byref(st)))
+        out = {f: getattr(st, f) for f, _ in OptStatus._fields_}
+        out["stop_reason"] = STOP_REASONS.get(st.stop, str(st.stop))
+        return out
+
+    def state(self):
+        """(alpha [d], W [M-1, E, N] unscaled or None) of the current iterate, as numpy arrays."""
+        s = self.system
+        alpha = np.empty(s.d)
+        W = np.empty((s.M - 1, s.E, s.N), dtype=np.complex128) if s.M > 1 else None
+        _check(_lib.qoc_opt_get(self.h, alpha.ctypes.data, W.ctypes.data if W is not None else None, QOC_HOST))
+        return alpha, W

@@ -35,6 +35,9 @@ MUTANTS = {
     "target transpose": ("p->target[2 * (c * s->E + e)] + I * p->target[2 * (c * s->E + e) + 1]",
                          "p->target[2 * (e * s->E + c)] + I * p->target[2 * (e * s->E + c) + 1]"),
     "essential row order": ("((e >> (p->q - 1 - j)) & 1)", "((e >> j) & 1)"),
+    "energy gradient conjugate": ("creal(conj(dj) * b * ph)", "creal(dj * b * ph)"),
+    "energy imaginary derivative": ("creal(conj(dj) * I * b * ph)", "creal(conj(dj) * b * ph)"),
+    "energy normalisation": ("c[j] / (2.0 * M_PI)", "c[j] / M_PI"),
 }
 
 
@@ -50,6 +53,7 @@ def test_planted_mistake_breaks_a_pin(name, tmp_path):
     subprocess.check_call(["gcc", "-O2", "-std=gnu99", "-fopenmp", "-fPIC", "-shared", "-o", str(lib), str(mut), "-lm"])
     env = dict(os.environ, QOC_ORACLE_LIB_OVERRIDE=str(lib), OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_optimizer_pins.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant '{name}' survived the pins:\n{r.stdout[-2000:]}"
