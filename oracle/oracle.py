@@ -43,6 +43,7 @@ class _Problem(ctypes.Structure):
         ("nf", ctypes.c_int), ("carrier", ctypes.c_void_p),
         ("d1", ctypes.c_int), ("T", ctypes.c_double), ("n_steps", ctypes.c_long),
         ("M", ctypes.c_int), ("mu", ctypes.c_double), ("target", ctypes.c_void_p),
+        ("dipole", ctypes.c_void_p),
     ]
 
 
@@ -94,10 +95,12 @@ class Problem:
             np.ascontiguousarray(w.cross_kerr if w.q > 1 else np.zeros(1), dtype=np.float64),
             np.ascontiguousarray(w.carriers.reshape(-1), dtype=np.float64),
             np.ascontiguousarray(w.target, dtype=np.complex128),
+            np.ascontiguousarray(w.dipole_or_zero if w.q > 1 else np.zeros(1), dtype=np.float64),
         ]
         a = self._arrays
         self.s = _Problem(w.q, w.L, a[0].ctypes.data, a[1].ctypes.data, a[2].ctypes.data, w.n_carriers,
-                          a[3].ctypes.data, w.n_splines, w.T, w.n_steps, w.n_windows, w.mu, a[4].ctypes.data)
+                          a[3].ctypes.data, w.n_splines, w.T, w.n_steps, w.n_windows, w.mu, a[4].ctypes.data,
+                          a[5].ctypes.data if w.dipole is not None else None)
 
     def ref(self):
         return ctypes.byref(self.s)

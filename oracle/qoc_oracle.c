@@ -11,8 +11,10 @@
  * What is computed, in the paper's notation (n replaced by the number of
  * essential states E when guard levels are present: the target acts on the
  * E essential rows and the guard rows of V are zero):
- *   model      H(t) = H_d + H_c(t), H_c = sum_j d_j a_j + conj(d_j) a_j^+  (Sec. 2, eqs. sys-ham, ctrl-ham)
- *              with the diagonal drift of the synthetic systems (detuning, anharmonicity, cross-Kerr).
+ *   model      H(t) = H_d + H_J + H_c(t), H_c = sum_j d_j a_j + conj(d_j) a_j^+  (Sec. 2, eqs. sys-ham, ctrl-ham)
+ *              with the diagonal drift H_d of the synthetic systems (detuning, anharmonicity, cross-Kerr)
+ *              and the dipole coupling of the chain H_J = sum_j J_j (a_{j+1}^+ a_j + a_{j+1} a_j^+)
+ *              (eq. sys-ham, nearest neighbours; zero for the synthetic systems).
  *   controls   d_j(t) = 2 pi sum_f exp(i Omega_jf t) sum_s (a1_jfs + i a2_jfs) B_s(t)   (Sec. 2, eq. dj-ctrl
  *              and the B-spline expansion below it); quadratic cardinal B-splines.
  *   windows    M windows, window m starts from W^{m-1} (W^0 = I)                     (Sec. 3, eqs. sch-op, sch-ic)
@@ -56,6 +58,7 @@ typedef struct {
     int M;                    /* windows                                       */
     double mu;                /* penalty coefficient                           */
     const double *target;     /* [2*E*E] E x E target, column-major            */
+    const double *dipole;     /* [q-1] rad/ns, J_j of qubits j, j+1; NULL = 0  */
 } orc_problem;
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_ENOTCONV = -4 };
@@ -166,7 +169,10 @@ static void controls(const orc_problem *p, const double *alpha, double t, cplx *
 
 /* ----------------------------------------------------------------------------- operators */
 
-/* out = H_c x with (a_j x)_r = sqrt(l_j+1) x_{r+stride_j}, (a_j^+ x)_r = sqrt(l_j) x_{r-stride_j}. */
+/* out = (H_c + H_J) x, the off-diagonal part of H, with
+ *   (a_j x)_r = sqrt(l_j+1) x_{r+stride_j},  (a_j^+ x)_r = sqrt(l_j) x_{r-stride_j},
+ *   (a_{j+1}^+ a_j x)_r = sqrt(l_{j+1}) sqrt(l_j+1) x_{r+stride_j-stride_{j+1}},
+ *   (a_{j+1} a_j^+ x)_r = sqrt(l_{j+1}+1) sqrt(l_j) x_{r-stride_j+stride_{j+1}}. */
 static void apply_Hc(const orc_sys *s, const cplx *c, const cplx *x, cplx *out)
 {
     const int q = s->p->q, L = s->p->L;
@@ -177,12 +183,21 @@ static void apply_Hc(const orc_sys *s, const cplx *c, const cplx *x, cplx *out)
             if (l < L - 1) acc += c[j] * sqrt((double)(l + 1)) * x[r + s->stride[j]];
             if (l > 0) acc += conj(c[j]) * sqrt((double)l) * x[r - s->stride[j]];
         }
+        if (s->p->dipole)
+            for (int j = 0; j + 1 < q; ++j) {
+                const int la = s->digit[r * q + j], lb = s->digit[r * q + j + 1];
+                const double J = s->p->dipole[j];
+                if (la < L - 1 && lb > 0)
+                    acc += J * sqrt((double)(la + 1)) * sqrt((double)lb) * x[r + s->stride[j] - s->stride[j + 1]];
+                if (la > 0 && lb < L - 1)
+                    acc += J * sqrt((double)la) * sqrt((double)(lb + 1)) * x[r - s->stride[j] + s->stride[j + 1]];
+            }
         out[r] = acc;
     }
 }
 
-/* Solve (I + sgn i dt/2 H) z = rhs for one column, H = diag(h) + H_c, by the
- * fixed point z <- D^{-1}(rhs - sgn i dt/2 H_c z), D = I + sgn i dt/2 diag(h),
+/* Solve (I + sgn i dt/2 H) z = rhs for one column, H = diag(h) + H_c + H_J, by the
+ * fixed point z <- D^{-1}(rhs - sgn i dt/2 (H_c + H_J) z), D = I + sgn i dt/2 diag(h),
  * iterated until the update is at rounding level.  work: N scratch entries. */
 static int imr_solve(const orc_sys *s, const cplx *c, int sgn, const cplx *rhs, cplx *z, cplx *work)
 {

@@ -44,6 +44,12 @@ PAPER_CARRIERS_MHZ = {
 }
 ANHARMONICITY_GHZ = -0.2      # per qubit
 CROSS_KERR_GHZ = 0.005        # nearest neighbours of the linear chain
+# Dipole-dipole coupling J_{j,j+1}/2pi [MHz] of the linear chain and the gate durations [ns]
+# and step counts of the QFT-4/8/16 test cases (Sec. 5, system-parameter and test-case tables).
+PAPER_DIPOLE_MHZ = 5.0
+PAPER_DURATION_NS = {2: 190.0, 3: 500.0, 4: 900.0}
+PAPER_STEPS = {2: 2252, 3: 19806, 4: 106072}
+PAPER_KNOT_SPACING_NS = 3.0
 
 
 def padded_carriers_mhz(q: int) -> List[List[float]]:
@@ -85,6 +91,15 @@ class Workload:
     window_states: str = "rollout_noise"   # or "qr"
     noise_std: float = 1e-3
     checkpoint_every: int = 0
+    dipole: Optional[np.ndarray] = None    # [q-1] rad/ns: J_{j,j+1} of the chain (None: no coupling)
+
+    @property
+    def dipole_or_zero(self) -> np.ndarray:
+        return np.zeros(max(self.q - 1, 0)) if self.dipole is None else np.asarray(self.dipole, dtype=float)
+
+    @property
+    def has_dipole(self) -> bool:
+        return self.dipole is not None and bool(np.any(np.asarray(self.dipole) != 0.0))
 
     @property
     def N(self) -> int:
@@ -113,7 +128,8 @@ class Workload:
 
 def make_system(name: str, q: int, L: int, T: float, n_steps: int, n_windows: int,
                 n_splines: int, mu: Optional[float] = None, window_states: str = "rollout_noise",
-                checkpoint_every: int = 0) -> Workload:
+                checkpoint_every: int = 0, dipole_mhz: float = 0.0,
+                cross_kerr_ghz: float = CROSS_KERR_GHZ) -> Workload:
     omega = np.array(PAPER_TRANSITION_GHZ[q])
     rot = omega.mean()
     carriers = np.array(padded_carriers_mhz(q)) * 1e-3 * TWO_PI
@@ -123,9 +139,10 @@ def make_system(name: str, q: int, L: int, T: float, n_steps: int, n_windows: in
         n_splines=int(n_splines), mu=float(2.0 / E if mu is None else mu),
         detuning=TWO_PI * (omega - rot),
         anharmonicity=np.full(q, TWO_PI * ANHARMONICITY_GHZ),
-        cross_kerr=np.full(max(q - 1, 0), TWO_PI * CROSS_KERR_GHZ),
+        cross_kerr=np.full(max(q - 1, 0), TWO_PI * cross_kerr_ghz),
         carriers=carriers, target=qft_target(E), window_states=window_states,
-        checkpoint_every=checkpoint_every)
+        checkpoint_every=checkpoint_every,
+        dipole=np.full(max(q - 1, 0), TWO_PI * dipole_mhz * 1e-3) if dipole_mhz else None)
 
 
 def c1() -> Workload:
@@ -144,6 +161,17 @@ def c3() -> Workload:
 
 
 CONFIGS = {"c1": c1, "c2": c2, "c3": c3}
+
+
+def paper_qft(q: int, n_windows: int, n_steps: Optional[int] = None, L: int = 2) -> Workload:
+    """The paper's QFT-4/8/16 system (Sec. 5): q qubits of L levels (n = 2^q without guard levels
+    at L = 2) in a chain with dipole coupling J = 5 MHz and no cross-Kerr term, the table's
+    transition and carrier frequencies, its gate duration and step count, and B-splines with a
+    knot spacing of 3 ns (d1 = ceil(T/3) + 2)."""
+    T = PAPER_DURATION_NS[q]
+    d1 = int(math.ceil(T / PAPER_KNOT_SPACING_NS - 1e-9)) + 2
+    return make_system(f"QFT-{2 ** q}", q, L, T, PAPER_STEPS[q] if n_steps is None else n_steps, n_windows, d1,
+                       dipole_mhz=PAPER_DIPOLE_MHZ, cross_kerr_ghz=0.0)
 
 
 def scaled(w: Workload, n_steps: int, n_windows: Optional[int] = None, n_splines: Optional[int] = None,

@@ -38,6 +38,23 @@ def drift_matrix(w):
     return H
 
 
+def dipole_matrix(w):
+    """sum_j J_j (a_{j+1}^+ a_j + a_{j+1} a_j^+) over the chain (eq. sys-ham, nearest neighbours)."""
+    q, L = w.q, w.L
+    a = lowering(L)
+    H = np.zeros((L ** q, L ** q), dtype=complex)
+    J = w.dipole_or_zero
+    for j in range(q - 1):
+        Aj, Ak = embed(a, j, q, L), embed(a, j + 1, q, L)
+        H += J[j] * (Ak.conj().T @ Aj + Ak @ Aj.conj().T)
+    return H
+
+
+def static_matrix(w):
+    """Time-independent part of H: the diagonal drift plus the dipole coupling."""
+    return drift_matrix(w) + dipole_matrix(w)
+
+
 def control_matrix(w, c):
     """sum_j c_j a_j + conj(c_j) a_j^+ with c_j = 2 pi d_j."""
     q, L = w.q, w.L
@@ -107,7 +124,7 @@ def dense_step(H, dt, U):
 def dense_objective(w, alpha, W):
     """P by dense stepping: W [M-1, E, N] column storage; returns (P, list of U^m as N x E)."""
     dt = w.T / w.n_steps
-    Hd = drift_matrix(w)
+    Hd = static_matrix(w)
     starts = window_starts_ref(w)
     V = embedded_target(w)
     Us = []

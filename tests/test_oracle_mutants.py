@@ -38,6 +38,9 @@ MUTANTS = {
     "energy gradient conjugate": ("creal(conj(dj) * b * ph)", "creal(dj * b * ph)"),
     "energy imaginary derivative": ("creal(conj(dj) * I * b * ph)", "creal(conj(dj) * b * ph)"),
     "energy normalisation": ("c[j] / (2.0 * M_PI)", "c[j] / M_PI"),
+    "dipole weight": ("J * sqrt((double)(la + 1)) * sqrt((double)lb)", "J * sqrt((double)la) * sqrt((double)lb)"),
+    "dipole direction": ("x[r + s->stride[j] - s->stride[j + 1]]", "x[r - s->stride[j] + s->stride[j + 1]]"),
+    "dipole neighbour": ("lb = s->digit[r * q + j + 1]", "lb = s->digit[r * q + j]"),
 }
 
 
@@ -54,6 +57,7 @@ def test_planted_mistake_breaks_a_pin(name, tmp_path):
     env = dict(os.environ, QOC_ORACLE_LIB_OVERRIDE=str(lib), OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_optimizer_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_optimizer_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_dipole_pins.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant '{name}' survived the pins:\n{r.stdout[-2000:]}"
