@@ -55,10 +55,12 @@ typedef struct qoc_ctx qoc_ctx;
 
 /* System description (copied by qoc_create).
  *
- * Hamiltonian (Sec. 2, eqs. sys-ham and ctrl-ham, with a diagonal drift):
- *   H(t) = H_d + sum_j [ 2 pi d_j(t) a_j + conj(2 pi d_j(t)) a_j^+ ],
+ * Hamiltonian (Sec. 2, eqs. sys-ham and ctrl-ham):
+ *   H(t) = H_d + H_J + sum_j [ 2 pi d_j(t) a_j + conj(2 pi d_j(t)) a_j^+ ],
  *   H_d  = sum_j [ detuning_j l_j + anharmonicity_j/2 l_j (l_j - 1) ]
  *        + sum_{j<q-1} cross_kerr_j l_j l_{j+1}             (rad/ns),
+ *   H_J  = sum_{j<q-1} dipole_j (a_{j+1}^+ a_j + a_{j+1} a_j^+)   (rad/ns; the
+ *          dipole coupling of eq. sys-ham on the nearest neighbours of the chain),
  * a_j the lowering operator of qubit j truncated to n_levels levels.
  * Controls (eq. dj-ctrl and the B-spline expansion of Sec. 2):
  *   d_j(t) = sum_f exp(i carrier_freq[j*n_carriers+f] t) sum_s (alpha1_jfs + i alpha2_jfs) B_s(t)
@@ -93,6 +95,10 @@ typedef struct qoc_system_desc {
   int32_t checkpoint_every;     /* >0: store states every this many steps per window
                                    and re-sync the reverse reconstruction there; 0: none */
   int32_t device;               /* HIP device ordinal                                 */
+  const double *dipole;         /* [q-1] rad/ns, host; NULL (or all zero) = no dipole
+                                   coupling.  The coupling keeps the digit-sum parity,
+                                   so the fixed point treats it Jacobi-style within a
+                                   colour; its count bound includes the term.         */
 } qoc_system_desc;
 
 /* Read-only facts about a context. */

@@ -37,24 +37,49 @@ bool finite_all(const double *p, size_t n) {
   return true;
 }
 
-// Largest eigenvalue of a + a^+ on L levels: the symmetric tridiagonal matrix
-// with zero diagonal and off-diagonal sqrt(1..L-1), by Sturm-sequence bisection.
-double ladder_norm(int L) {
-  auto count_below = [L](double x) {
+// Largest eigenvalue of the symmetric tridiagonal matrix with zero diagonal and
+// squared off-diagonal entries e2[0..n-2], by Sturm-sequence bisection (an upper
+// bound to bisection accuracy).
+double tridiag_max_eig(const std::vector<double> &e2) {
+  const int n = (int)e2.size() + 1;
+  auto count_below = [&](double x) {
     int cnt = 0;
     double d = -x;
-    for (int i = 0; i < L; ++i) {
-      if (i > 0) d = -x - (double)i / (d == 0.0 ? 1e-300 : d);
+    for (int i = 0; i < n; ++i) {
+      if (i > 0) d = -x - e2[i - 1] / (d == 0.0 ? 1e-300 : d);
       if (d < 0) ++cnt;
     }
     return cnt;
   };
-  double lo = 0.0, hi = 2.0 * std::sqrt((double)(L - 1)) + 1.0;
+  double hi = 1.0;
+  for (double v : e2) hi += 2.0 * std::sqrt(v);
+  double lo = 0.0;
   for (int it = 0; it < 200; ++it) {
     const double mid = 0.5 * (lo + hi);
-    if (count_below(mid) == L) hi = mid; else lo = mid;
+    if (count_below(mid) == n) hi = mid; else lo = mid;
   }
   return hi;
+}
+
+// ||a + a^+||_2 on L levels: off-diagonal entries sqrt(1..L-1).
+double ladder_norm(int L) {
+  std::vector<double> e2;
+  for (int i = 1; i < L; ++i) e2.push_back((double)i);
+  return tridiag_max_eig(e2);
+}
+
+// ||b^+ a + b a^+||_2 on two L-level systems.  The operator keeps n = l_a + l_b; on
+// each sector it is tridiagonal in l_a with entries sqrt(l_a) sqrt(n - l_a + 1).
+double exchange_norm(int L) {
+  double best = 0.0;
+  for (int n = 1; n <= 2 * (L - 1); ++n) {
+    const int k0 = std::max(0, n - (L - 1)), k1 = std::min(n, L - 1);
+    if (k1 <= k0) continue;
+    std::vector<double> e2;
+    for (int k = k0 + 1; k <= k1; ++k) e2.push_back((double)k * (double)(n - k + 1));
+    best = std::max(best, tridiag_max_eig(e2));
+  }
+  return best;
 }
 
 }  // namespace
@@ -144,6 +169,7 @@ int qoc_create(const qoc_system_desc *desc, qoc_ctx **out) {
   const int nf = D.n_carriers, d1 = D.n_splines, M = D.n_windows;
   const long long NT = D.n_steps;
   if (!finite_all(D.detuning, q) || !finite_all(D.anharmonicity, q) || (D.cross_kerr && !finite_all(D.cross_kerr, q - 1)) ||
+      (D.dipole && !finite_all(D.dipole, q - 1)) ||
       !finite_all(D.carrier_freq, (size_t)q * nf) || !finite_all(D.target, 2 * (size_t)E * E))
     return fail(QOC_EINVAL, "non-finite system parameter");
   // the target must be unitary (eq. mod-infid assumes V^+ V = I)
@@ -160,9 +186,12 @@ int qoc_create(const qoc_system_desc *desc, qoc_ctx **out) {
     if (worst > 1e-10) return fail(QOC_EINVAL, "target is not unitary");
   }
   const int fp64 = D.precision == QOC_FP64;
+  int hop = 0;
+  if (D.dipole)
+    for (int j = 0; j + 1 < q; ++j) hop |= D.dipole[j] != 0.0;
   int ld = 0, cpw = 1;
   int shape = 0;
-  if (!qoc::layout_for(q, L, fp64, &ld, &cpw, &shape))
+  if (!qoc::layout_for(q, L, fp64, hop, &ld, &cpw, &shape))
     return fail(QOC_EUNSUPPORTED, "no kernel instance for q=" + std::to_string(q) + " L=" + std::to_string(L));
 
   HIP_OR_RETURN(hipSetDevice(D.device));
@@ -207,6 +236,16 @@ int qoc_create(const qoc_system_desc *desc, qoc_ctx **out) {
   s.q = q; s.L = L; s.N = (int)N; s.E = E; s.nf = nf; s.d1 = d1; s.M = M; s.NT = NT;
   s.T = D.T; s.dt = dt; s.dtau = D.T / (double)(d1 - 2); s.mu = D.mu;
   s.nu_L = ladder_norm(L);
+  s.hop = hop;
+  s.beta = 0.0;
+  for (int j = 0; j < 8; ++j) s.hop_c[j] = 0.0;
+  if (hop) {
+    const double nx = exchange_norm(L);
+    for (int j = 0; j + 1 < q; ++j) {
+      s.hop_c[j] = 0.5 * dt * D.dipole[j];
+      s.beta += std::fabs(s.hop_c[j]) * nx;
+    }
+  }
   s.fp64 = fp64; s.ld = ld; s.cpw = cpw; s.ncg = (E + cpw - 1) / cpw; s.maxlen = maxlen;
   s.ckpt_every = (D.checkpoint_every > 0 && D.checkpoint_every < maxlen) ? D.checkpoint_every : 0;
   s.ncp = s.ckpt_every ? (int)((maxlen - 1) / s.ckpt_every) : 0;

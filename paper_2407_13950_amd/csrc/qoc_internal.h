@@ -16,6 +16,9 @@ struct DevSys {
   long long NT;
   double T, dt, dtau, mu;
   double nu_L;              // ||a + a^+||_2 for L levels (fixed-point contraction bound)
+  int hop;                  // 1: dipole exchange terms of the chain present (kernel variant)
+  double hop_c[8];          // (dt/2) J_j for the pairs (j, j+1), j < q-1
+  double beta;              // ||D^{-1} (dt/2) H_J||_2 bound: (dt/2) sum_j |J_j| ||a^+ b + a b^+||_2
   int fp64;                 // 1: propagation in double, 0: float
   int ld;                   // lane digits of the register layout
   int cpw;                  // state columns per wavefront
@@ -52,8 +55,9 @@ struct DevSys {
 enum { STATUS_NOTCONV = 1 };
 
 // Layout chosen for a (q, L) pair: lane digits, columns per wavefront and the
-// kernel-instance index.  Returns false when no kernel instance exists for the pair.
-bool layout_for(int q, int L, int fp64, int *ld, int *cpw, int *shape);
+// kernel-instance index (the dipole variant when hop is set).  Returns false when
+// no kernel instance exists for the pair.
+bool layout_for(int q, int L, int fp64, int hop, int *ld, int *cpw, int *shape);
 
 // Phases of one evaluation, launched in this order on one stream:
 // objective = CONTROLS, FORWARD, BOUNDARY; gradient adds BACKWARD, PROJECT, GRAD_W.

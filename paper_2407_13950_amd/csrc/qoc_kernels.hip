@@ -201,6 +201,14 @@ struct Lane {
   // multiplies every step, so in FP32 its rounding error would accumulate
   // linearly over a window; the remainder removes that drift.
   T mr[G::EPL], mi[G::EPL], mrl[G::EPL], mil[G::EPL];
+  // Dipole exchange weights, (dt/2) J_j included (set by init_hop, dead otherwise).
+  // Term A of the pair (j, j+1) reads the row with l_j + 1, l_{j+1} - 1 (weight
+  // sqrt(l_j + 1) sqrt(l_{j+1})), term B the row with l_j - 1, l_{j+1} + 1 (weight
+  // sqrt(l_j) sqrt(l_{j+1} + 1)), both zero off the ends of the digits.
+  static constexpr int NPL = LD > 1 ? LD - 1 : 1;
+  T hc[Q];                      // (dt/2) J_j
+  T hla[NPL], hlb[NPL];         // lane-digit pairs (R+jj, R+jj+1): full A and B weights
+  T hsa, hsb;                   // pair (R-1, R): (dt/2) J_{R-1} sqrt(l_R), (dt/2) J_{R-1} sqrt(l_R + 1)
 
   __device__ void init(const DevSys &s, int cg, T *xbuf) {
     xb = xbuf;
@@ -236,6 +244,29 @@ struct Lane {
       mi[e] = (T)b;
       mrl[e] = (T)((a - 1.0) - (double)mr[e]);
       mil[e] = (T)(b - (double)mi[e]);
+    }
+  }
+  __device__ void init_hop(const DevSys &s) {
+    int l[LD > 0 ? LD : 1];
+#pragma unroll
+    for (int jj = 0; jj < LD; ++jj) l[jj] = valid ? (sub / G::lstride(jj)) % L : 0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) hc[j] = (T)(j + 1 < Q ? s.hop_c[j] : 0.0);
+#pragma unroll
+    for (int jj = 0; jj < NPL; ++jj) {
+      hla[jj] = hlb[jj] = (T)0;
+      if (jj + 1 < LD && valid) {
+        const double J = s.hop_c[G::R + jj];
+        const int a = l[jj], b = l[jj + 1];
+        hla[jj] = (T)((a < L - 1 && b > 0) ? J * sqrt((double)(a + 1)) * sqrt((double)b) : 0.0);
+        hlb[jj] = (T)((a > 0 && b < L - 1) ? J * sqrt((double)a) * sqrt((double)(b + 1)) : 0.0);
+      }
+    }
+    hsa = hsb = (T)0;
+    if (LD > 0 && G::R >= 1 && valid) {
+      const double J = s.hop_c[G::R - 1];
+      hsa = (T)(J * sqrt((double)l[0]));
+      hsb = (T)(l[0] < L - 1 ? J * sqrt((double)(l[0] + 1)) : 0.0);
     }
   }
   // row of the state column held in register slot e
@@ -328,9 +359,151 @@ __device__ __forceinline__ void lane_digit_terms(const Lane<T, Q, L, LD> &ln, co
   }
 }
 
+// ---------------------------------------------------------------------------- dipole exchange terms
+
+// S += (dt/2) H_J v, H_J = sum_j J_j (a_{j+1}^+ a_j + a_{j+1} a_j^+) (eq. sys-ham, chain),
+// on NO output slots for NRHS right-hand sides.  The exchange keeps the digit sum,
+// so in the red-black layout (C >= 0) an output slot of colour C reads the current
+// values of colour C; the caller passes them, own[b*NO + o] with o the slot within
+// the colour (C < 0: plain layout, all EPL slots).  Register digits: only the pair
+// (leading digit, next register digit) occurs (R <= 2).  Lane digits go through the
+// lane exchange; PUT writes own to it first, otherwise the caller's record of this
+// layout is still in the buffer.  Every read of a value that lies outside the digit
+// range meets a zero weight.
+
+// Red-black output slot (s0, t) of colour C: source slot of the pair (l0 +- 1, l' -+ 1)
+// when l0 and one other digit change together (same lane and leading+register pair, or
+// leading digit with the neighbouring lane): the source has the other lead parity, so
+// A (l0 + 1) sits at s0 + b and B (l0 - 1) at s0 - 1 + b, b the output's lead parity.
+template <int HALF>
+__device__ __forceinline__ constexpr int lead_up(int s0, int b) { return s0 + b < HALF ? s0 + b : s0; }
+template <int HALF>
+__device__ __forceinline__ constexpr int lead_dn(int s0, int b) { return s0 - 1 + b >= 0 ? s0 - 1 + b : s0; }
+
+template <typename T, int Q, int L, int LD, int C, int NRHS, int JJ>
+__device__ __forceinline__ void hop_lane_pairs(const Lane<T, Q, L, LD> &ln, T *Sr, T *Si) {
+  using G = Geo<T, Q, L, LD>;
+  if constexpr (JJ + 1 < LD) {
+    constexpr int NO = C >= 0 ? G::H : G::EPL;
+    constexpr int NV = 2 * NO * NRHS;
+    constexpr int OFF = G::lstride(JJ) - G::lstride(JJ + 1);   // A: l_jj + 1, l_jj+1 - 1
+    T a[NV], b[NV];
+    xget<T, NV, OFF>(ln.xb, ln.lane, a);
+    xget<T, NV, -OFF>(ln.xb, ln.lane, b);
+#pragma unroll
+    for (int i = 0; i < NO * NRHS; ++i) {
+      Sr[i] = fma_(ln.hla[JJ], a[2 * i], Sr[i]);
+      Si[i] = fma_(ln.hla[JJ], a[2 * i + 1], Si[i]);
+      Sr[i] = fma_(ln.hlb[JJ], b[2 * i], Sr[i]);
+      Si[i] = fma_(ln.hlb[JJ], b[2 * i + 1], Si[i]);
+    }
+    hop_lane_pairs<T, Q, L, LD, C, NRHS, JJ + 1>(ln, Sr, Si);
+  }
+}
+
+template <typename T, int Q, int L, int LD, int C, int NRHS, bool PUT>
+__device__ __forceinline__ void hop_terms(const Lane<T, Q, L, LD> &ln, const T *ownr, const T *owni, T *Sr, T *Si) {
+  using G = Geo<T, Q, L, LD>;
+  constexpr bool RBL = C >= 0;
+  constexpr int NO = RBL ? G::H : G::EPL;
+  constexpr int NV = 2 * NO * NRHS;
+  constexpr int R = G::R;
+  static_assert(!RBL || G::RB, "a colour needs the red-black layout");
+  static_assert(RBL ? R <= 2 : R <= 1, "exchange pairs of two register digits other than the leading pair");
+  // register pair (0, 1), red-black with R = 2: the leading digit l0 and digit 1 (t's only digit)
+  if constexpr (RBL && R == 2 && Q >= 2) {
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+      const int s0 = o / G::RT, t = o % G::RT;
+      const int beta = G::tpar(t) ^ C;
+      const int bl = ln.par ^ beta;
+      const int l1 = t % L;                     // digit 1 (stride 1 within t)
+#pragma unroll
+      for (int b = 0; b < NRHS; ++b) {
+        if (l1 > 0) {                           // A: l0 + 1, l1 - 1
+          const int ta = t - 1;
+          const int i0 = b * NO + s0 * G::RT + ta, i1 = b * NO + lead_up<G::HALF>(s0, 1) * G::RT + ta;
+          const T vr = bl ? ownr[i1] : ownr[i0], vi = bl ? owni[i1] : owni[i0];
+          const T w = ln.hc[0] * (T)sqrt((double)l1) * ln.wup[beta][s0];
+          Sr[b * NO + o] = fma_(w, vr, Sr[b * NO + o]);
+          Si[b * NO + o] = fma_(w, vi, Si[b * NO + o]);
+        }
+        if (l1 < L - 1) {                       // B: l0 - 1, l1 + 1
+          const int tb = t + 1;
+          const int i0 = b * NO + lead_dn<G::HALF>(s0, 0) * G::RT + tb, i1 = b * NO + s0 * G::RT + tb;
+          const T vr = bl ? ownr[i1] : ownr[i0], vi = bl ? owni[i1] : owni[i0];
+          const T w = ln.hc[0] * (T)sqrt((double)(l1 + 1)) * ln.wdn[beta][s0];
+          Sr[b * NO + o] = fma_(w, vr, Sr[b * NO + o]);
+          Si[b * NO + o] = fma_(w, vi, Si[b * NO + o]);
+        }
+      }
+    }
+  }
+  if constexpr (LD > 0) {
+    if constexpr (PUT) {
+      T rec[NV];
+#pragma unroll
+      for (int i = 0; i < NO * NRHS; ++i) {
+        rec[2 * i] = ownr[i];
+        rec[2 * i + 1] = owni[i];
+      }
+      wave_sync();
+      xput<T, NV>(ln.xb, ln.lane, rec);
+      wave_sync();
+    }
+    // pair (R-1, R): register digit R-1 and lane digit 0.  A reads the lane one step
+    // down in lane digit 0 (l_R - 1), B the lane one step up.
+    {
+      constexpr int ST = G::lstride(0);
+      T dn[NV], up[NV];
+      xget<T, NV, -ST>(ln.xb, ln.lane, dn);
+      xget<T, NV, ST>(ln.xb, ln.lane, up);
+#pragma unroll
+      for (int o = 0; o < NO; ++o) {
+#pragma unroll
+        for (int b = 0; b < NRHS; ++b) {
+          const int so = b * NO + o;
+          if constexpr (RBL && R == 1) {        // digit R-1 is the leading digit
+            const int s0 = o;                   // RT = 1
+            const int beta = C;
+            const int bl = ln.par ^ beta;
+            const int ia0 = b * NO + s0, ia1 = b * NO + lead_up<G::HALF>(s0, 1);
+            const int ib0 = b * NO + lead_dn<G::HALF>(s0, 0), ib1 = b * NO + s0;
+            const T ar = bl ? dn[2 * ia1] : dn[2 * ia0], ai = bl ? dn[2 * ia1 + 1] : dn[2 * ia0 + 1];
+            const T br = bl ? up[2 * ib1] : up[2 * ib0], bi = bl ? up[2 * ib1 + 1] : up[2 * ib0 + 1];
+            const T wa = ln.hsa * ln.wup[beta][s0], wb = ln.hsb * ln.wdn[beta][s0];
+            Sr[so] = fma_(wa, ar, Sr[so]);
+            Si[so] = fma_(wa, ai, Si[so]);
+            Sr[so] = fma_(wb, br, Sr[so]);
+            Si[so] = fma_(wb, bi, Si[so]);
+          } else {
+            // digit R-1 known at compile time: in t (red-black, R = 2) or in e (plain layout, R = 1)
+            const int la = RBL ? (o % G::RT) % L : G::rdigit(o, R - 1);
+            constexpr int DS = RBL ? 1 : G::rstride(R - 1);
+            if (la < L - 1) {
+              const int src = b * NO + o + DS;
+              const T w = ln.hsa * (T)sqrt((double)(la + 1));
+              Sr[so] = fma_(w, dn[2 * src], Sr[so]);
+              Si[so] = fma_(w, dn[2 * src + 1], Si[so]);
+            }
+            if (la > 0) {
+              const int src = b * NO + o - DS;
+              const T w = ln.hsb * (T)sqrt((double)la);
+              Sr[so] = fma_(w, up[2 * src], Sr[so]);
+              Si[so] = fma_(w, up[2 * src + 1], Si[so]);
+            }
+          }
+        }
+      }
+    }
+    hop_lane_pairs<T, Q, L, LD, C, NRHS, 0>(ln, Sr, Si);
+    wave_sync();
+  }
+}
+
 // S = (dt/2) H_c v for this lane's entries.  cr/ci: per-qubit scaled control
 // c'_j = (dt/2) 2 pi d_j; the coefficient of a_j is c'_j, of a_j^+ conj(c'_j).
-template <typename T, int Q, int L, int LD>
+template <typename T, int Q, int L, int LD, bool HOP>
 __device__ __forceinline__ void apply_Hc(const Lane<T, Q, L, LD> &ln, const T *cr, const T *ci,
                                          const T *lor, const T *loi, const T *hir, const T *hii,
                                          const T *vr, const T *vi, T *Sr, T *Si) {
@@ -356,6 +529,7 @@ __device__ __forceinline__ void apply_Hc(const Lane<T, Q, L, LD> &ln, const T *c
     }
   }
   lane_digit_terms<T, Q, L, LD, G::EPL>(ln, lor, loi, hir, hii, n, Sr, Si);
+  if constexpr (HOP) hop_terms<T, Q, L, LD, -1, 1, false>(ln, vr, vi, Sr, Si);   // reads the record above
 }
 
 // Per-step control coefficients: c'_j for register digits, per-lane lowering
@@ -499,8 +673,9 @@ __device__ __forceinline__ void jacobi_update(const Lane<T, Q, L, LD> &ln, int e
 }
 
 // Red-black half sweep: refresh the increment on the slots of colour C from the
-// current values of colour 1-C.
-template <typename T, int Q, int L, int LD, bool REV, int C>
+// current values of colour 1-C (HOP: and the exchange terms from colour C's own
+// current values).
+template <typename T, int Q, int L, int LD, bool REV, int C, bool HOP>
 __device__ __forceinline__ void half_sweep(const Lane<T, Q, L, LD> &ln, const Coef<T, Q, L, LD> &cf, const T *ur,
                                            const T *ui, const T *xr, const T *xi, T *wr, T *wi) {
   using G = Geo<T, Q, L, LD>;
@@ -512,6 +687,15 @@ __device__ __forceinline__ void half_sweep(const Lane<T, Q, L, LD> &ln, const Co
     vi[IN + o] = ui[IN + o] + wi[IN + o];
   }
   apply_half<T, Q, L, LD, C>(ln, cf, vr, vi, Sr, Si);
+  if constexpr (HOP) {
+    T orr[G::H], ori[G::H];
+#pragma unroll
+    for (int o = 0; o < G::H; ++o) {
+      orr[o] = ur[OUT + o] + wr[OUT + o];
+      ori[o] = ui[OUT + o] + wi[OUT + o];
+    }
+    hop_terms<T, Q, L, LD, C, 1, true>(ln, orr, ori, Sr, Si);
+  }
 #pragma unroll
   for (int o = 0; o < G::H; ++o)
     jacobi_update<T, Q, L, LD, REV>(ln, OUT + o, Sr[o], Si[o], xr[OUT + o], xi[OUT + o], wr[OUT + o], wi[OUT + o]);
@@ -525,8 +709,10 @@ __device__ __forceinline__ void half_sweep(const Lane<T, Q, L, LD> &ln, const Co
 // parity, so the two colours are refreshed alternately, each from the other's
 // newest values; nit counts these half sweeps, each costing half an iteration.
 // The increment is O(dt |H|) |u| small, so its FP32 rounding enters the FP64
-// state only at that scale.
-template <typename T, int Q, int L, int LD, bool REV>
+// state only at that scale.  HOP: the dipole exchange H_J joins H_c in the
+// iteration; it keeps the digit-sum parity, so a half sweep takes it from its own
+// colour's current values (Jacobi-style within the colour).
+template <typename T, int Q, int L, int LD, bool REV, bool HOP>
 __device__ __forceinline__ void solve_increment(const Lane<T, Q, L, LD> &ln, int nit, const Coef<T, Q, L, LD> &cf,
                                                 const T *ur, const T *ui, T *wr, T *wi) {
   using G = Geo<T, Q, L, LD>;
@@ -540,10 +726,10 @@ __device__ __forceinline__ void solve_increment(const Lane<T, Q, L, LD> &ln, int
   if constexpr (G::RB) {
     int h = 0;
     for (; h + 1 < nit; h += 2) {
-      half_sweep<T, Q, L, LD, REV, 0>(ln, cf, ur, ui, xr, xi, wr, wi);
-      half_sweep<T, Q, L, LD, REV, 1>(ln, cf, ur, ui, xr, xi, wr, wi);
+      half_sweep<T, Q, L, LD, REV, 0, HOP>(ln, cf, ur, ui, xr, xi, wr, wi);
+      half_sweep<T, Q, L, LD, REV, 1, HOP>(ln, cf, ur, ui, xr, xi, wr, wi);
     }
-    if (h < nit) half_sweep<T, Q, L, LD, REV, 0>(ln, cf, ur, ui, xr, xi, wr, wi);
+    if (h < nit) half_sweep<T, Q, L, LD, REV, 0, HOP>(ln, cf, ur, ui, xr, xi, wr, wi);
   } else {
     T vr[G::EPL], vi[G::EPL], Sr[G::EPL], Si[G::EPL];
     for (int it = 0; it < nit; ++it) {
@@ -552,7 +738,7 @@ __device__ __forceinline__ void solve_increment(const Lane<T, Q, L, LD> &ln, int
         vr[e] = ur[e] + wr[e];
         vi[e] = ui[e] + wi[e];
       }
-      apply_Hc<T, Q, L, LD>(ln, cf.cr, cf.ci, cf.lor, cf.loi, cf.hir, cf.hii, vr, vi, Sr, Si);
+      apply_Hc<T, Q, L, LD, HOP>(ln, cf.cr, cf.ci, cf.lor, cf.loi, cf.hir, cf.hii, vr, vi, Sr, Si);
 #pragma unroll
       for (int e = 0; e < G::EPL; ++e) jacobi_update<T, Q, L, LD, REV>(ln, e, Sr[e], Si[e], xr[e], xi[e], wr[e], wi[e]);
     }
@@ -606,7 +792,7 @@ __device__ __forceinline__ void last_inner_lane(const Lane<T, Q, L, LD> &ln, T (
 // state and adjoint): their records travel in one exchange, so a step has half as
 // many LDS round trips.  Each result equals half_sweep on its own bit for bit.
 // LAST: also the lane-digit inner products of the final z and y (last_inner_lane).
-template <typename T, int Q, int L, int LD, bool REV, int C, bool LAST = false>
+template <typename T, int Q, int L, int LD, bool REV, int C, bool HOP, bool LAST = false>
 __device__ __forceinline__ void half_sweep2(const Lane<T, Q, L, LD> &ln, const Coef<T, Q, L, LD> &cf,
                                             const T *uar, const T *uai, const T *xar, const T *xai, T *war, T *wai,
                                             const T *ubr, const T *ubi, const T *xbr, const T *xbi, T *wbr,
@@ -631,6 +817,17 @@ __device__ __forceinline__ void half_sweep2(const Lane<T, Q, L, LD> &ln, const C
   apply_half_regs<T, Q, L, LD, C>(ln, cf, var, vai, Sr, Si);
   apply_half_regs<T, Q, L, LD, C>(ln, cf, vbr, vbi, Sr + G::H, Si + G::H);
   lane_digit_terms<T, Q, L, LD, 2 * G::H>(ln, cf.lor, cf.loi, cf.hir, cf.hii, n, Sr, Si);
+  if constexpr (HOP) {
+    T orr[2 * G::H], ori[2 * G::H];
+#pragma unroll
+    for (int o = 0; o < G::H; ++o) {
+      orr[o] = uar[OUT + o] + war[OUT + o];
+      ori[o] = uai[OUT + o] + wai[OUT + o];
+      orr[G::H + o] = ubr[OUT + o] + wbr[OUT + o];
+      ori[G::H + o] = ubi[OUT + o] + wbi[OUT + o];
+    }
+    hop_terms<T, Q, L, LD, C, 2, true>(ln, orr, ori, Sr, Si);
+  }
 #pragma unroll
   for (int o = 0; o < G::H; ++o) {
     jacobi_update<T, Q, L, LD, REV>(ln, OUT + o, Sr[o], Si[o], xar[OUT + o], xai[OUT + o], war[OUT + o], wai[OUT + o]);
@@ -659,7 +856,7 @@ constexpr bool fused_inner() { return (L % 2) == 0 && XPre<T>::value; }
 // bit-identical to solve_increment on its own.  When fused_inner, the lane-digit
 // inner products of the solutions are left in s1, s2 (entries R..q-1), taken in
 // the last half sweep; nit >= 1.
-template <typename T, int Q, int L, int LD, bool REV>
+template <typename T, int Q, int L, int LD, bool REV, bool HOP>
 __device__ __forceinline__ void solve_increment2(const Lane<T, Q, L, LD> &ln, int nit, const Coef<T, Q, L, LD> &cf,
                                                  const T *ar, const T *ai, T *war, T *wai,
                                                  const T *br, const T *bi, T *wbr, T *wbi, T *s1, T *s2) {
@@ -678,25 +875,25 @@ __device__ __forceinline__ void solve_increment2(const Lane<T, Q, L, LD> &ln, in
     int h = 0;
     if constexpr (fused_inner<T, L>()) {
       for (; h + 2 < nit; h += 2) {
-        half_sweep2<T, Q, L, LD, REV, 0>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
-        half_sweep2<T, Q, L, LD, REV, 1>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+        half_sweep2<T, Q, L, LD, REV, 0, HOP>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+        half_sweep2<T, Q, L, LD, REV, 1, HOP>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
       }
       if (nit - h == 2) {
-        half_sweep2<T, Q, L, LD, REV, 0>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
-        half_sweep2<T, Q, L, LD, REV, 1, true>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi, s1, s2);
+        half_sweep2<T, Q, L, LD, REV, 0, HOP>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+        half_sweep2<T, Q, L, LD, REV, 1, HOP, true>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi, s1, s2);
       } else {
-        half_sweep2<T, Q, L, LD, REV, 0, true>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi, s1, s2);
+        half_sweep2<T, Q, L, LD, REV, 0, HOP, true>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi, s1, s2);
       }
     } else {
       for (; h + 1 < nit; h += 2) {
-        half_sweep2<T, Q, L, LD, REV, 0>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
-        half_sweep2<T, Q, L, LD, REV, 1>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+        half_sweep2<T, Q, L, LD, REV, 0, HOP>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+        half_sweep2<T, Q, L, LD, REV, 1, HOP>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
       }
-      if (h < nit) half_sweep2<T, Q, L, LD, REV, 0>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+      if (h < nit) half_sweep2<T, Q, L, LD, REV, 0, HOP>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
     }
   } else {
-    solve_increment<T, Q, L, LD, REV>(ln, nit, cf, ar, ai, war, wai);
-    solve_increment<T, Q, L, LD, REV>(ln, nit, cf, br, bi, wbr, wbi);
+    solve_increment<T, Q, L, LD, REV, HOP>(ln, nit, cf, ar, ai, war, wai);
+    solve_increment<T, Q, L, LD, REV, HOP>(ln, nit, cf, br, bi, wbr, wbi);
   }
 }
 
@@ -707,11 +904,12 @@ __device__ __forceinline__ void solve_increment2(const Lane<T, Q, L, LD> &ln, in
 // registers, u_{k+1} = u_k + 2 w_k, and is written as U^m(t_m); optional
 // checkpoints U_{k0 + i*C} are written on the way.  ROLLOUT: a single window over
 // all steps from W^0, writing the states at the window boundaries instead.
-template <typename T, int Q, int L, int LD, bool ROLLOUT>
+template <typename T, int Q, int L, int LD, bool ROLLOUT, bool HOP>
 __device__ __forceinline__ void forward_item(const DevSys &s, int m, int cg, double *Wout, double *Uout, T *xb) {
   using G = Geo<T, Q, L, LD>;
   Lane<T, Q, L, LD> ln;
   ln.init(s, cg, xb);
+  if constexpr (HOP) ln.init_hop(s);
 
   double udr[G::EPL], udi[G::EPL];
 #pragma unroll
@@ -754,7 +952,7 @@ __device__ __forceinline__ void forward_item(const DevSys &s, int m, int cg, dou
       ur[e] = (T)udr[e];
       ui[e] = (T)udi[e];
     }
-    solve_increment<T, Q, L, LD, false>(ln, kit, cf, ur, ui, wr, wi);
+    solve_increment<T, Q, L, LD, false, HOP>(ln, kit, cf, ur, ui, wr, wi);
 #pragma unroll
     for (int e = 0; e < G::EPL; ++e) {   // u_{k+1} = 2 z - u_k = u_k + 2 w
       udr[e] += 2.0 * (double)wr[e];
@@ -777,14 +975,14 @@ __device__ __forceinline__ void forward_item(const DevSys &s, int m, int cg, dou
   for (int e = 0; e < G::EPL; ++e) dst[ln.row(e)] = double2{udr[e], udi[e]};
 }
 
-template <typename T, int Q, int L, int LD, bool ROLLOUT>
+template <typename T, int Q, int L, int LD, bool ROLLOUT, bool HOP>
 __global__ __launch_bounds__(64) void k_forward(DevSys s, double *Wout, double *Uout, int nitems) {
   const int item = xcd_item(blockIdx.x, gridDim.x);
   if (item >= nitems) return;
   __shared__ __align__(16) T xb[xchg_bytes<T>() / sizeof(T)];
   xchg_clear(xb);
-  if (ROLLOUT) forward_item<T, Q, L, LD, true>(s, 0, item, Wout, Uout, xb);
-  else forward_item<T, Q, L, LD, false>(s, item / s.ncg, item % s.ncg, nullptr, nullptr, xb);
+  if (ROLLOUT) forward_item<T, Q, L, LD, true, HOP>(s, 0, item, Wout, Uout, xb);
+  else forward_item<T, Q, L, LD, false, HOP>(s, item / s.ncg, item % s.ncg, nullptr, nullptr, xb);
 }
 
 // Slot holding, in the lane one lane-digit step away, the row with the same
@@ -957,12 +1155,13 @@ struct SeriesBuf {
 // Re<z, i dH z>/E = 0 to the control gradient (dH Hermitian); only gamma V/E^2 is
 // propagated, and the W-gradient adds the dropped part back exactly:
 // Lambda^M(t_{M-1}) = -W^{M-1}/E + (propagated part)  (App. B, eq. back-prop-2).
-template <typename T, int Q, int L, int LD>
+template <typename T, int Q, int L, int LD, bool HOP>
 __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T *red, T *xb) {
   using G = Geo<T, Q, L, LD>;
   const int item = m * s.ncg + cg;
   Lane<T, Q, L, LD> ln;
   ln.init(s, cg, xb);
+  if constexpr (HOP) ln.init_hop(s);
 
   double udr[G::EPL], udi[G::EPL], ldr[G::EPL], ldi[G::EPL];
   {
@@ -1012,7 +1211,7 @@ __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T 
       li[e] = (T)ldi[e];
     }
     T s1[Q], s2[Q];
-    solve_increment2<T, Q, L, LD, true>(ln, kit, cf, ur, ui, wur, wui, lr, li, wlr, wli, s1, s2);
+    solve_increment2<T, Q, L, LD, true, HOP>(ln, kit, cf, ur, ui, wur, wui, lr, li, wlr, wli, s1, s2);
     T zr[G::EPL], zi[G::EPL], yr[G::EPL], yi[G::EPL];
 #pragma unroll
     for (int e = 0; e < G::EPL; ++e) {
@@ -1080,14 +1279,14 @@ __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T 
   for (int e = 0; e < G::EPL; ++e) l0[ln.row(e)] = double2{ldr[e], ldi[e]};
 }
 
-template <typename T, int Q, int L, int LD>
+template <typename T, int Q, int L, int LD, bool HOP>
 __global__ __launch_bounds__(64) void k_backward(DevSys s, int nitems) {
   const int item = xcd_item(blockIdx.x, gridDim.x);
   if (item >= nitems) return;
   __shared__ T red[red_elems<T>()];
   __shared__ __align__(16) T xb[xchg_bytes<T>() / sizeof(T)];
   xchg_clear(xb);
-  backward_item<T, Q, L, LD>(s, item / s.ncg, item % s.ncg, red, xb);
+  backward_item<T, Q, L, LD, HOP>(s, item / s.ncg, item % s.ncg, red, xb);
 }
 
 // ---------------------------------------------------------------------------- small FP64 kernels
@@ -1102,16 +1301,38 @@ __global__ __launch_bounds__(64) void k_backward(DevSys s, int nitems) {
 //    block of the iteration matrix (2-norm <= rho), so after h half sweeps the colours
 //    carry <= rho^(h+1) |z| and <= rho^h |z|, together <= rho^h sqrt(1 + rho^2) |z|;
 //    h is the smallest count with that <= solve_tol.
+//  with the dipole exchange H_J (beta >= |D^{-1}| ||(dt/2) H_J||_2 > 0), the start error is
+//    <= (rho + beta)|z|; a Jacobi iteration contracts by rho + beta, and a half sweep of
+//    colour C bounds that colour's error by rho (other colour) + beta (its own).
 __device__ void kit_block(const DevSys &s) {
   if (threadIdx.x != 0) return;
   const double rho = (double)__uint_as_float(*s.rho_bits) * (1.0 + 1e-6);
   *s.rho_bits = 0u;                  // reset for the next evaluation
   const bool rb = (s.L % 2) == 0;
+  const double beta = s.beta, tau = rho + beta;
   int K = 1;
-  double err = rb ? rho * sqrt(1.0 + rho * rho) : rho * rho;
-  while (err > s.solve_tol && K < 64) { err *= rho; ++K; }
+  double err;
+  if (beta == 0.0) {
+    err = rb ? rho * sqrt(1.0 + rho * rho) : rho * rho;
+    while (err > s.solve_tol && K < 64) { err *= rho; ++K; }
+  } else if (!rb) {                  // Jacobi on H_c + H_J: tau^(K+1)
+    err = tau * tau;
+    while (err > s.solve_tol && K < 64) { err *= tau; ++K; }
+  } else {
+    // Red-black with the exchange term: a half sweep of colour C bounds that colour's
+    // error by rho * (other colour) + beta * (its own previous error); both start at tau.
+    double x0 = tau, x1 = tau;
+    x0 = rho * x1 + beta * x0;
+    err = sqrt(x0 * x0 + x1 * x1);
+    while (err > s.solve_tol && K < 64) {
+      ++K;
+      if (K & 1) x0 = rho * x1 + beta * x0;
+      else x1 = rho * x0 + beta * x1;
+      err = sqrt(x0 * x0 + x1 * x1);
+    }
+  }
   if (s.kit_fixed <= 0) *s.kit = K;
-  if (s.kit_fixed <= 0 && (err > s.solve_tol || rho >= 0.5)) atomicOr(s.status, (int)STATUS_NOTCONV);
+  if (s.kit_fixed <= 0 && (err > s.solve_tol || tau >= 0.5)) atomicOr(s.status, (int)STATUS_NOTCONV);
 }
 
 // (dt/2) * 2 pi d_j(t_{k+1/2}) for every step; B_s(t) = B(t/dtau + 1/2 - s); and the
@@ -1322,9 +1543,9 @@ struct Kernels {
   void (*bwd)(DevSys, int);
 };
 
-template <typename T, int Q, int L, int LD>
+template <typename T, int Q, int L, int LD, bool HOP>
 Kernels make() {
-  return Kernels{k_forward<T, Q, L, LD, false>, k_forward<T, Q, L, LD, true>, k_backward<T, Q, L, LD>};
+  return Kernels{k_forward<T, Q, L, LD, false, HOP>, k_forward<T, Q, L, LD, true, HOP>, k_backward<T, Q, L, LD, HOP>};
 }
 
 // (q, L) -> lane digits, chosen so that each lane holds at most four entries
@@ -1336,19 +1557,20 @@ Kernels make() {
   X(4, 2, 2) X(4, 3, 3) X(4, 4, 3) \
   X(5, 2, 3) X(6, 2, 4)
 
+// Kernel-instance index: the shape, plus N_SHAPES for the dipole variant.
 #define X(Q_, L_, LD_) SHAPE_##Q_##_##L_,
 enum ShapeId { QOC_SHAPES(X) N_SHAPES };
 #undef X
 
 template <typename T>
-bool lookup(int q, int L, Kernels *k, int *ld, int *cpw, int *shape) {
-#define X(Q_, L_, LD_)                                                 \
-  if (q == Q_ && L == L_) {                                            \
-    if (k) *k = make<T, Q_, L_, LD_>();                                \
-    *ld = LD_;                                                         \
-    *cpw = Geo<T, Q_, L_, LD_>::CPW;                                   \
-    if (shape) *shape = SHAPE_##Q_##_##L_;                             \
-    return true;                                                       \
+bool lookup(int q, int L, bool hop, Kernels *k, int *ld, int *cpw, int *shape) {
+#define X(Q_, L_, LD_)                                                             \
+  if (q == Q_ && L == L_) {                                                        \
+    if (k) *k = hop ? make<T, Q_, L_, LD_, true>() : make<T, Q_, L_, LD_, false>(); \
+    *ld = LD_;                                                                     \
+    *cpw = Geo<T, Q_, L_, LD_>::CPW;                                               \
+    if (shape) *shape = SHAPE_##Q_##_##L_ + (hop ? N_SHAPES : 0);                  \
+    return true;                                                                   \
   }
   QOC_SHAPES(X)
 #undef X
@@ -1364,8 +1586,11 @@ __global__ __launch_bounds__(64) void k_forward_batch(const DevSys *sys, const i
   const int4 it = items[blockIdx.x];
   const DevSys s = sys[it.x];
   switch (it.w) {
-#define X(Q_, L_, LD_) \
-    case SHAPE_##Q_##_##L_: forward_item<T, Q_, L_, LD_, false>(s, it.y, it.z, nullptr, nullptr, xb); break;
+#define X(Q_, L_, LD_)                                                                                     \
+    case SHAPE_##Q_##_##L_: forward_item<T, Q_, L_, LD_, false, false>(s, it.y, it.z, nullptr, nullptr, xb); break; \
+    case N_SHAPES + SHAPE_##Q_##_##L_:                                                                     \
+      forward_item<T, Q_, L_, LD_, false, true>(s, it.y, it.z, nullptr, nullptr, xb);                     \
+      break;
     QOC_SHAPES(X)
 #undef X
     default: break;
@@ -1380,8 +1605,9 @@ __global__ __launch_bounds__(64) void k_backward_batch(const DevSys *sys, const 
   const int4 it = items[blockIdx.x];
   const DevSys s = sys[it.x];
   switch (it.w) {
-#define X(Q_, L_, LD_) \
-    case SHAPE_##Q_##_##L_: backward_item<T, Q_, L_, LD_>(s, it.y, it.z, red, xb); break;
+#define X(Q_, L_, LD_)                                                                      \
+    case SHAPE_##Q_##_##L_: backward_item<T, Q_, L_, LD_, false>(s, it.y, it.z, red, xb); break; \
+    case N_SHAPES + SHAPE_##Q_##_##L_: backward_item<T, Q_, L_, LD_, true>(s, it.y, it.z, red, xb); break;
     QOC_SHAPES(X)
 #undef X
     default: break;
@@ -1400,7 +1626,7 @@ template <typename T>
 int phase_T(const DevSys &s, int phase, hipStream_t st, double *Wout, double *Ufinal) {
   Kernels K;
   int ld, cpw;
-  if (!lookup<T>(s.q, s.L, &K, &ld, &cpw, nullptr)) return (int)hipErrorInvalidValue;
+  if (!lookup<T>(s.q, s.L, s.hop != 0, &K, &ld, &cpw, nullptr)) return (int)hipErrorInvalidValue;
   const int nitems = s.M * s.ncg;
   switch (phase) {
     case PHASE_CONTROLS:
@@ -1484,8 +1710,9 @@ int small_blocks(const DevSys &s, int kind) {
   }
 }
 
-bool layout_for(int q, int L, int fp64, int *ld, int *cpw, int *shape) {
-  return fp64 ? lookup<double>(q, L, nullptr, ld, cpw, shape) : lookup<float>(q, L, nullptr, ld, cpw, shape);
+bool layout_for(int q, int L, int fp64, int hop, int *ld, int *cpw, int *shape) {
+  return fp64 ? lookup<double>(q, L, hop != 0, nullptr, ld, cpw, shape)
+              : lookup<float>(q, L, hop != 0, nullptr, ld, cpw, shape);
 }
 
 int launch_phase(const DevSys &s, int phase, hipStream_t st, double *Wout, double *Ufinal) {

@@ -52,6 +52,7 @@ class SystemDesc(ctypes.Structure):
         ("n_windows", ctypes.c_int32), ("mu", ctypes.c_double), ("target", ctypes.c_void_p),
         ("precision", ctypes.c_int32), ("fixed_point_iters", ctypes.c_int32), ("solve_tol", ctypes.c_double),
         ("checkpoint_every", ctypes.c_int32), ("device", ctypes.c_int32),
+        ("dipole", ctypes.c_void_p),
     ]
 
 
@@ -158,12 +159,15 @@ class System:
                       np.ascontiguousarray(w.anharmonicity, dtype=np.float64),
                       np.ascontiguousarray(w.cross_kerr if w.q > 1 else np.zeros(1), dtype=np.float64),
                       np.ascontiguousarray(np.asarray(w.carriers).reshape(-1), dtype=np.float64),
-                      np.ascontiguousarray(w.target, dtype=np.complex128)]
+                      np.ascontiguousarray(w.target, dtype=np.complex128),
+                      np.ascontiguousarray(w.dipole_or_zero if w.q > 1 else np.zeros(1), dtype=np.float64)]
         k = self._keep
         ck = w.checkpoint_every if checkpoint_every is None else checkpoint_every
+        dip = getattr(w, "dipole", None)
         self.desc = SystemDesc(w.q, w.L, k[0].ctypes.data, k[1].ctypes.data, k[2].ctypes.data, w.n_carriers,
                                k[3].ctypes.data, w.n_splines, w.T, w.n_steps, w.n_windows, w.mu, k[4].ctypes.data,
-                               QOC_FP64 if precision == "fp64" else QOC_FP32, fixed_point_iters, solve_tol, ck, device)
+                               QOC_FP64 if precision == "fp64" else QOC_FP32, fixed_point_iters, solve_tol, ck, device,
+                               k[5].ctypes.data if dip is not None else None)
         h = ctypes.c_void_p()
         _check(lib.qoc_create(ctypes.byref(self.desc), ctypes.byref(h)))
         self.h = h

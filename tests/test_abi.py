@@ -4,6 +4,7 @@ touches a device."""
 import ctypes
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -28,14 +29,31 @@ def test_library_exports_every_declared_function():
     assert sorted(qoc.EXPORTED) == names
 
 
-def test_struct_layout_matches_header():
-    """Offsets of qoc_system_desc / qoc_info as laid out by the C compiler on x86-64 (LP64)."""
-    assert ctypes.sizeof(qoc.SystemDesc) == 120
-    assert ctypes.sizeof(qoc.Info) == 48
-    off = {"detuning": 8, "n_carriers": 32, "T": 56, "n_steps": 64, "target": 88, "solve_tol": 104, "device": 116}
-    for f, o in off.items():
-        assert getattr(qoc.SystemDesc, f).offset == o, f
-    assert qoc.Info.n_window_doubles.offset == 16 and qoc.Info.device_bytes.offset == 40
+def test_struct_layout_matches_header(tmp_path):
+    """Size and every field offset of the binding's structs equal what the C compiler lays out
+    for include/qoc.h (a small program built with gcc prints sizeof/offsetof)."""
+    structs = {"qoc_system_desc": qoc.SystemDesc, "qoc_info": qoc.Info, "qoc_timings": qoc.Timings,
+               "qoc_opt_desc": qoc.OptDesc, "qoc_opt_status": qoc.OptStatus}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "qoc.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    got = {}
+    for line in out:
+        if line:
+            c, f, v = line.split()
+            got[(c, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
 
 
 def _desc(w, **kw):
@@ -78,6 +96,10 @@ def test_create_rejects_non_unitary_target_and_non_finite_parameters():
     det[0] = np.inf
     d, keep = _desc(w.replace(detuning=det))
     assert lib.qoc_create(ctypes.byref(d), ctypes.byref(h)) == qoc.QOC_EINVAL
+    dip = np.array([np.nan])                            # dipole coupling of the one pair
+    d, keep = _desc(w, dipole=dip.ctypes.data)
+    assert lib.qoc_create(ctypes.byref(d), ctypes.byref(h)) == qoc.QOC_EINVAL
+    assert b"non-finite" in lib.qoc_last_error()
 
 
 def test_create_reports_unsupported_shapes():
