@@ -37,6 +37,8 @@ def algorithmic_flops(w, kit):
     q, L = w.q, w.L
     ladder = 16.0 * q * (L - 1) / L          # complex MACs of the nonzero ladder terms, per entry
     per_iter = ladder + 8.0                  # + z = x -/+ i D^-1 S
+    if getattr(w, "has_dipole", False):      # + real-weight exchange terms of the q-1 pairs (4 flops each)
+        per_iter += 8.0 * (q - 1) * ((L - 1) / L) ** 2
     sweeps = kit / 2.0 if L % 2 == 0 else float(kit)
     fwd = sweeps * per_iter + 10.0           # + D^-1 u and u' = 2z - u
     bwd = 2.0 * fwd + ladder                 # two right-hand sides + the per-step inner products
@@ -169,27 +171,32 @@ def bench_serve(rate, n_requests, plain_requests, seed, budget_gb, log):
     return out
 
 
-def bench_optimize(caps, chunk, seed, log):
-    """The quadratic-penalty L-BFGS driver (Sec. 3, Sec. 5 settings) on the three configured systems
-    from the roll-out of the clipped random start: wall time per iteration and the time at which
-    the roll-out-infidelity estimate first falls below 1e-1, 1e-2, 1e-3 (checked every `chunk`
-    iterations), each run capped at its iteration count."""
+# The paper's optimisation results (Sec. 5, optimisation-results table): runtime to the stopping
+# rule on its CPU cluster, single-window reference and best multiple-shooting case.
+PAPER_OPT_SECONDS = {("QFT-4", 1): 2.3, ("QFT-4", 16): 0.5, ("QFT-8", 1): 145.0, ("QFT-8", 32): 23.0,
+                     ("QFT-16", 1): 59 * 60.0, ("QFT-16", 64): 12 * 60.0}
+
+
+def bench_optimize(runs, seed, log, time_limit):
+    """The quadratic-penalty L-BFGS driver (Sec. 3 with the Sec. 5 settings) on the paper's QFT
+    systems (2 levels, dipole chain, table durations and step counts), from the roll-out of a
+    random start in [-10, 10] MHz: wall time and iterations until the roll-out-infidelity estimate
+    falls below 1e-3 (the paper's stopping rule), also the first passes below 1e-1 and 1e-2
+    (checked every 50 iterations, every 10 for one window).  `runs`: [(qubits, windows, cap)]."""
     import torch
     from paper_2407_13950_amd import qoc, workloads as WL
     out = {}
-    for name, mk, cap in (("2-qubit", WL.c1, caps[0]), ("3-qubit", WL.c2, caps[1]), ("4-qubit", WL.c3, caps[2])):
-        if cap <= 0:
-            continue
-        w = mk()
+    for q, M, cap in runs:
+        w = WL.paper_qft(q, M)
         s = qoc.System(w, precision="fp32")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         opt = qoc.Optimizer(s, WL.gen_alpha(w, seed), None)
         st0 = opt.run(0)
-        t_start = time.perf_counter() - t0
         marks = {}
         st = st0
-        while st["stop"] == 0 and st["iterations"] < cap:
+        chunk = 50 if M > 1 else 10
+        while st["stop"] == 0 and st["iterations"] < cap and time.perf_counter() - t0 < time_limit:
             st = opt.run(min(chunk, cap - st["iterations"]))
             el = time.perf_counter() - t0
             for thr in (1e-1, 1e-2, 1e-3):
@@ -197,15 +204,64 @@ def bench_optimize(caps, chunk, seed, log):
                     marks[str(thr)] = {"iterations": st["iterations"], "seconds": el}
         el = time.perf_counter() - t0
         its = max(st["iterations"], 1)
-        out[name] = {"workload": f"{w.name} N_T={w.n_steps} M={w.n_windows} variables={w.d + 2 * w.n_w}",
-                     "iterations": st["iterations"], "cap": cap, "evaluations": st["evaluations"],
-                     "seconds": el, "start_seconds": t_start,
-                     "ms_per_iteration": 1e3 * (el - t_start) / its, "stop": st["stop_reason"],
-                     "F": [st0["F"], st["F"]], "J": [st0["J"], st["J"]], "penalty": st["penalty"],
-                     "estimate": [st0["estimate"], st["estimate"]], "estimate_below": marks}
-        log(f"optimise {name}: {st['iterations']} iterations in {el:.2f} s, estimate "
-            f"{st0['estimate']:.3e} -> {st['estimate']:.3e}, J {st['J']:.3e}, marks {marks}")
+        key = f"{w.name} M={M}"
+        out[key] = {"workload": f"{w.name}: q={w.q} L={w.L} T={w.T} ns N_T={w.n_steps} M={M} d={w.d} "
+                                f"variables={w.d + 2 * w.n_w}",
+                    "converged": st["stop_reason"] == "estimate", "seconds": el, "iterations": st["iterations"],
+                    "evaluations": st["evaluations"], "ms_per_iteration": 1e3 * el / its, "cap": cap,
+                    "stop": st["stop_reason"], "estimate": [st0["estimate"], st["estimate"]],
+                    "J": [st0["J"], st["J"]], "penalty": st["penalty"], "estimate_below": marks,
+                    "paper_seconds": PAPER_OPT_SECONDS.get((w.name, M))}
+        log(f"optimise {key}: {st['iterations']} iterations in {el:.2f} s ({st['stop_reason']}), estimate "
+            f"{st0['estimate']:.3e} -> {st['estimate']:.3e}, J {st['J']:.3e}")
         opt.close()
+        s.close()
+    return out
+
+
+def bench_dipole(steps, warmup, seed, log):
+    """Evaluations with the dipole-coupled drift: the 4-qubit system with a 5 MHz exchange chain
+    added (same sizes as the headline), and the paper's QFT-16 system at M = 64.  Inputs resident
+    in HBM; returns evals/s, phases and the backward kernel's roofline fraction."""
+    import numpy as np
+    import torch
+    from paper_2407_13950_amd import qoc, workloads as WL
+    out = {}
+    c3 = WL.c3()
+    cases = (("4-qubit + dipole", c3.replace(dipole=np.full(3, 2 * math.pi * 5e-3), name="C3-q4L4-J")),
+             ("QFT-16 M=64", WL.paper_qft(4, 64)))
+    for name, w in cases:
+        s = qoc.System(w, precision="fp32")
+        s.set_controls(WL.gen_alpha(w, seed))
+        Wt, _ = s.rollout(device=True)
+        W = (Wt + torch.tensor(WL.gen_noise(w, seed), device="cuda")).contiguous()
+        s.set_window_states(W)
+        P = torch.empty(1, dtype=torch.float64, device="cuda")
+        terms = torch.empty(4 + w.n_windows, dtype=torch.float64, device="cuda")
+        ga = torch.empty(w.d, dtype=torch.float64, device="cuda")
+        gW = torch.empty((w.n_windows - 1, w.E, w.N), dtype=torch.complex128, device="cuda")
+        for _ in range(warmup):
+            s.gradient_into(P, terms, ga, gW)
+        torch.cuda.synchronize()
+        s.synchronize()
+        s.enable_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.gradient_into(P, terms, ga, gW)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        tm = s.timings()
+        f_fwd, f_bwd = algorithmic_flops(w, tm["fixed_point_iters"])
+        ach = f_bwd / (tm["backward"] * 1e-3) / 1e12
+        out[name] = {"workload": f"{w.name}: q={w.q} L={w.L} N_T={w.n_steps} M={w.n_windows} J/2pi=5 MHz",
+                     "value": steps / el, "unit": "evals/s", "steps": steps,
+                     "fixed_point_iters": tm["fixed_point_iters"],
+                     "phases_ms": {k: tm[k] for k in qoc.PHASES},
+                     "roofline": {"kernel": f"k_backward<float, {w.q}, {w.L}, {s.info['lane_digits']}, true>",
+                                  "bound": "alu", "achieved": ach, "peak": PEAK_FP32_VECTOR_TFLOPS,
+                                  "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VECTOR_TFLOPS}}
+        log(f"dipole {name}: {steps / el:.1f} evals/s, backward {tm['backward']:.3f} ms, "
+            f"{ach:.1f} TFLOP/s, count {tm['fixed_point_iters']}")
         s.close()
     return out
 
@@ -220,14 +276,17 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=3, help="steps of the plain FP64 form timed for comparison")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU-oracle sample size (0: skip)")
     ap.add_argument("--seed", type=int, default=2024)
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched-mix, serving and optimisation measurements")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched-mix, serving, dipole and optimisation measurements")
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-plain-requests", type=int, default=600)
     ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate as a fraction of the batched mix rate")
     ap.add_argument("--hbm-budget-gb", type=float, default=6.0)
-    ap.add_argument("--opt-iters", default="600,600,200",
-                    help="iteration caps of the optimisation runs on the 2/3/4-qubit systems (0: skip)")
+    ap.add_argument("--opt-runs", default="2:16:3000,2:1:500,3:32:6000,3:1:400",
+                    help="optimisation runs on the paper's QFT systems, qubits:windows:iteration-cap, "
+                         "comma-separated (empty: skip); e.g. add 4:16:10000 for QFT-16 (~3 min)")
+    ap.add_argument("--opt-seconds", type=float, default=60.0, help="wall-time limit per optimisation run")
+    ap.add_argument("--dipole-steps", type=int, default=10, help="timed steps of the dipole systems (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -295,7 +354,8 @@ def main():
     flops = f_bwd if dominant == "backward" else f_fwd
     achieved = flops / (tm[dominant] * 1e-3) / 1e12
     tname = "float" if args.precision == "fp32" else "double"
-    kname = f"k_backward<{tname}, 4, 4, 3>" if dominant == "backward" else f"k_forward<{tname}, 4, 4, 3, false>"
+    kname = (f"k_backward<{tname}, 4, 4, 3, false>" if dominant == "backward"
+             else f"k_forward<{tname}, 4, 4, 3, false, false>")
     value = args.steps / elapsed
     result = {
         "metric": "objective+gradient evals/s at 4 qubits",
@@ -355,10 +415,16 @@ def main():
         except Exception as e:   # the headline line must still be printed
             result["extras_error"] = repr(e)
             log(f"extras failed: {e!r}")
-        caps = [int(c) for c in args.opt_iters.split(",")]
-        if any(caps):
+        if args.dipole_steps > 0:
             try:
-                result["optimisation"] = bench_optimize(caps, 50, args.seed, log)
+                result["dipole"] = bench_dipole(args.dipole_steps, 5, args.seed, log)
+            except Exception as e:
+                result["dipole_error"] = repr(e)
+                log(f"dipole systems failed: {e!r}")
+        runs = [tuple(int(x) for x in r.split(":")) for r in args.opt_runs.split(",") if r]
+        if runs:
+            try:
+                result["optimisation"] = bench_optimize(runs, args.seed, log, args.opt_seconds)
             except Exception as e:
                 result["optimisation_error"] = repr(e)
                 log(f"optimisation failed: {e!r}")

@@ -112,9 +112,11 @@ __device__ __forceinline__ double bspline2(double x) {
 // weight.  LDS operations of one wavefront complete in issue order, so the
 // exchange needs no wait, only compiler ordering (wave_sync).
 constexpr int kGuard = 16;                      // >= every lane-digit stride
-constexpr int kXchgMaxNV = 8;                   // values per record: 2*EPL with EPL <= 4
-template <typename T>
-constexpr int xchg_bytes() { return (64 + 2 * kGuard) * kXchgMaxNV * (int)sizeof(T); }
+// Values per record: 2*EPL with EPL <= 4; twice that with the dipole exchange, whose
+// records also carry the refreshed colour's own values.
+constexpr int kXchgMaxNV = 16;
+template <typename T, bool HOP>
+constexpr int xchg_bytes() { return (64 + 2 * kGuard) * (HOP ? 16 : 8) * (int)sizeof(T); }
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -123,10 +125,10 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Zero the whole exchange buffer (64 lanes, 16 bytes per store).
-template <typename T>
+template <typename T, bool HOP>
 __device__ __forceinline__ void xchg_clear(T *buf) {
   float4 *p = reinterpret_cast<float4 *>(buf);
-  for (int i = threadIdx.x; i < xchg_bytes<T>() / 16; i += 64) p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int i = threadIdx.x; i < xchg_bytes<T, HOP>() / 16; i += 64) p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
   wave_sync();
 }
 
@@ -318,9 +320,14 @@ struct LaneGets {
 // record only where it is used.
 template <typename T> struct XPre { static constexpr bool value = sizeof(T) == 4; };
 
-template <typename T, int Q, int L, int LD, int K>
+// Planes after the first record's: a second record of KO complex values (the
+// dipole exchange's own-colour values) rides in the same exchange.
+template <typename T, int K>
+__device__ __forceinline__ constexpr int xtail() { return XRec<T, 2 * K>::NP * XRec<T, 2 * K>::PSTRIDE; }
+
+template <typename T, int Q, int L, int LD, int K, int KO = 0>
 __device__ __forceinline__ void lane_exchange(const Lane<T, Q, L, LD> &ln, const T *vr, const T *vi,
-                                              T (*n)[2 * K]) {
+                                              T (*n)[2 * K], const T *wr = nullptr, const T *wi = nullptr) {
   if constexpr (LD > 0) {
     T rec[2 * K];
 #pragma unroll
@@ -329,6 +336,16 @@ __device__ __forceinline__ void lane_exchange(const Lane<T, Q, L, LD> &ln, const
       rec[2 * o + 1] = vi[o];
     }
     xput<T, 2 * K>(ln.xb, ln.lane, rec);
+    if constexpr (KO > 0) {
+      static_assert(XRec<T, 2 * KO>::PE == XRec<T, 2 * K>::PE, "records of one exchange share the plane width");
+      T rec2[2 * KO];
+#pragma unroll
+      for (int o = 0; o < KO; ++o) {
+        rec2[2 * o] = wr[o];
+        rec2[2 * o + 1] = wi[o];
+      }
+      xput<T, 2 * KO>(ln.xb + xtail<T, K>(), ln.lane, rec2);
+    }
     wave_sync();
     if constexpr (XPre<T>::value) {
       LaneGets<T, LD, K, 0>::load(ln, n);
@@ -366,10 +383,11 @@ __device__ __forceinline__ void lane_digit_terms(const Lane<T, Q, L, LD> &ln, co
 // so in the red-black layout (C >= 0) an output slot of colour C reads the current
 // values of colour C; the caller passes them, own[b*NO + o] with o the slot within
 // the colour (C < 0: plain layout, all EPL slots).  Register digits: only the pair
-// (leading digit, next register digit) occurs (R <= 2).  Lane digits go through the
-// lane exchange; PUT writes own to it first, otherwise the caller's record of this
-// layout is still in the buffer.  Every read of a value that lies outside the digit
-// range meets a zero weight.
+// (leading digit, next register digit) occurs (R <= 2).  Lane digits read the other
+// lanes' own-colour values from the records at `base`, written by the caller's lane
+// exchange (red-black: a second record behind the ladder's; plain layout: the
+// ladder's record itself).  Every read of a value that lies outside the digit range
+// meets a zero weight.
 
 // Red-black output slot (s0, t) of colour C: source slot of the pair (l0 +- 1, l' -+ 1)
 // when l0 and one other digit change together (same lane and leading+register pair, or
@@ -381,15 +399,15 @@ template <int HALF>
 __device__ __forceinline__ constexpr int lead_dn(int s0, int b) { return s0 - 1 + b >= 0 ? s0 - 1 + b : s0; }
 
 template <typename T, int Q, int L, int LD, int C, int NRHS, int JJ>
-__device__ __forceinline__ void hop_lane_pairs(const Lane<T, Q, L, LD> &ln, T *Sr, T *Si) {
+__device__ __forceinline__ void hop_lane_pairs(const Lane<T, Q, L, LD> &ln, const T *base, T *Sr, T *Si) {
   using G = Geo<T, Q, L, LD>;
   if constexpr (JJ + 1 < LD) {
     constexpr int NO = C >= 0 ? G::H : G::EPL;
     constexpr int NV = 2 * NO * NRHS;
     constexpr int OFF = G::lstride(JJ) - G::lstride(JJ + 1);   // A: l_jj + 1, l_jj+1 - 1
     T a[NV], b[NV];
-    xget<T, NV, OFF>(ln.xb, ln.lane, a);
-    xget<T, NV, -OFF>(ln.xb, ln.lane, b);
+    xget<T, NV, OFF>(base, ln.lane, a);
+    xget<T, NV, -OFF>(base, ln.lane, b);
 #pragma unroll
     for (int i = 0; i < NO * NRHS; ++i) {
       Sr[i] = fma_(ln.hla[JJ], a[2 * i], Sr[i]);
@@ -397,12 +415,13 @@ __device__ __forceinline__ void hop_lane_pairs(const Lane<T, Q, L, LD> &ln, T *S
       Sr[i] = fma_(ln.hlb[JJ], b[2 * i], Sr[i]);
       Si[i] = fma_(ln.hlb[JJ], b[2 * i + 1], Si[i]);
     }
-    hop_lane_pairs<T, Q, L, LD, C, NRHS, JJ + 1>(ln, Sr, Si);
+    hop_lane_pairs<T, Q, L, LD, C, NRHS, JJ + 1>(ln, base, Sr, Si);
   }
 }
 
-template <typename T, int Q, int L, int LD, int C, int NRHS, bool PUT>
-__device__ __forceinline__ void hop_terms(const Lane<T, Q, L, LD> &ln, const T *ownr, const T *owni, T *Sr, T *Si) {
+template <typename T, int Q, int L, int LD, int C, int NRHS>
+__device__ __forceinline__ void hop_terms(const Lane<T, Q, L, LD> &ln, const T *base, const T *ownr, const T *owni,
+                                          T *Sr, T *Si) {
   using G = Geo<T, Q, L, LD>;
   constexpr bool RBL = C >= 0;
   constexpr int NO = RBL ? G::H : G::EPL;
@@ -440,24 +459,13 @@ __device__ __forceinline__ void hop_terms(const Lane<T, Q, L, LD> &ln, const T *
     }
   }
   if constexpr (LD > 0) {
-    if constexpr (PUT) {
-      T rec[NV];
-#pragma unroll
-      for (int i = 0; i < NO * NRHS; ++i) {
-        rec[2 * i] = ownr[i];
-        rec[2 * i + 1] = owni[i];
-      }
-      wave_sync();
-      xput<T, NV>(ln.xb, ln.lane, rec);
-      wave_sync();
-    }
     // pair (R-1, R): register digit R-1 and lane digit 0.  A reads the lane one step
     // down in lane digit 0 (l_R - 1), B the lane one step up.
     {
       constexpr int ST = G::lstride(0);
       T dn[NV], up[NV];
-      xget<T, NV, -ST>(ln.xb, ln.lane, dn);
-      xget<T, NV, ST>(ln.xb, ln.lane, up);
+      xget<T, NV, -ST>(base, ln.lane, dn);
+      xget<T, NV, ST>(base, ln.lane, up);
 #pragma unroll
       for (int o = 0; o < NO; ++o) {
 #pragma unroll
@@ -496,7 +504,7 @@ __device__ __forceinline__ void hop_terms(const Lane<T, Q, L, LD> &ln, const T *
         }
       }
     }
-    hop_lane_pairs<T, Q, L, LD, C, NRHS, 0>(ln, Sr, Si);
+    hop_lane_pairs<T, Q, L, LD, C, NRHS, 0>(ln, base, Sr, Si);
     wave_sync();
   }
 }
@@ -529,7 +537,7 @@ __device__ __forceinline__ void apply_Hc(const Lane<T, Q, L, LD> &ln, const T *c
     }
   }
   lane_digit_terms<T, Q, L, LD, G::EPL>(ln, lor, loi, hir, hii, n, Sr, Si);
-  if constexpr (HOP) hop_terms<T, Q, L, LD, -1, 1, false>(ln, vr, vi, Sr, Si);   // reads the record above
+  if constexpr (HOP) hop_terms<T, Q, L, LD, -1, 1>(ln, ln.xb, vr, vi, Sr, Si);   // reads the record above
 }
 
 // Per-step control coefficients: c'_j for register digits, per-lane lowering
@@ -542,16 +550,28 @@ struct Coef {
   T ur[2][NH], ui[2][NH], dr[2][NH], di[2][NH];
 };
 
-template <typename T, int Q, int L, int LD>
-__device__ __forceinline__ void step_coeffs(const Lane<T, Q, L, LD> &ln, const T *ctrl, long long k,
-                                            Coef<T, Q, L, LD> &c) {
+// The control values of step k (uniform across the wavefront).  Layouts with several
+// columns per wavefront (small systems, few wavefronts per SIMD, so a window's chain
+// of steps is latency-bound) load them one step ahead; the large layouts keep the
+// registers for occupancy.
+template <typename G>
+constexpr bool ctrl_ahead() { return G::CPW > 1; }
+
+template <typename T, int Q>
+__device__ __forceinline__ void load_ctrl(const T *ctrl, long long k, typename C2<T>::type *v) {
   using V2 = typename C2<T>::type;
   const V2 *cp = reinterpret_cast<const V2 *>(ctrl) + k * Q;
 #pragma unroll
+  for (int j = 0; j < Q; ++j) v[j] = cp[j];
+}
+
+template <typename T, int Q, int L, int LD>
+__device__ __forceinline__ void step_coeffs(const Lane<T, Q, L, LD> &ln, const typename C2<T>::type *v,
+                                            Coef<T, Q, L, LD> &c) {
+#pragma unroll
   for (int j = 0; j < Q; ++j) {
-    const V2 v = cp[j];
-    c.cr[j] = v.x;
-    c.ci[j] = v.y;
+    c.cr[j] = v[j].x;
+    c.ci[j] = v[j].y;
   }
 #pragma unroll
   for (int jj = 0; jj < LD; ++jj) {
@@ -644,17 +664,20 @@ __device__ __forceinline__ void apply_half_regs(const Lane<T, Q, L, LD> &ln, con
 }
 
 // S = (dt/2) H_c v on the H slots of colour C, reading only the slots of colour 1-C.
-template <typename T, int Q, int L, int LD, int C>
+// HOP: plus (dt/2) H_J from colour C's current values own (sent in the same exchange).
+template <typename T, int Q, int L, int LD, int C, bool HOP = false>
 __device__ __forceinline__ void apply_half(const Lane<T, Q, L, LD> &ln, const Coef<T, Q, L, LD> &cf,
-                                           const T *vr, const T *vi, T *Sr, T *Si) {
+                                           const T *vr, const T *vi, T *Sr, T *Si, const T *owr = nullptr,
+                                           const T *owi = nullptr) {
   using G = Geo<T, Q, L, LD>;
   constexpr int IN = (1 - C) * G::H;
   // lane digits: output slot o reads slot IN + o of the neighbouring lanes (the
   // colour flips with the lane parity); requested first, used last
   T n[2 * (LD > 0 ? LD : 1)][2 * G::H];
-  lane_exchange<T, Q, L, LD, G::H>(ln, vr + IN, vi + IN, n);
+  lane_exchange<T, Q, L, LD, G::H, HOP ? G::H : 0>(ln, vr + IN, vi + IN, n, owr, owi);
   apply_half_regs<T, Q, L, LD, C>(ln, cf, vr, vi, Sr, Si);
   lane_digit_terms<T, Q, L, LD, G::H>(ln, cf.lor, cf.loi, cf.hir, cf.hii, n, Sr, Si);
+  if constexpr (HOP) hop_terms<T, Q, L, LD, C, 1>(ln, ln.xb + xtail<T, G::H>(), owr, owi, Sr, Si);
 }
 
 __device__ __forceinline__ int kit_of(const DevSys &s) { return s.kit_fixed > 0 ? s.kit_fixed : *s.kit; }
@@ -686,16 +709,15 @@ __device__ __forceinline__ void half_sweep(const Lane<T, Q, L, LD> &ln, const Co
     vr[IN + o] = ur[IN + o] + wr[IN + o];
     vi[IN + o] = ui[IN + o] + wi[IN + o];
   }
-  apply_half<T, Q, L, LD, C>(ln, cf, vr, vi, Sr, Si);
+  T orr[G::H], ori[G::H];
   if constexpr (HOP) {
-    T orr[G::H], ori[G::H];
 #pragma unroll
     for (int o = 0; o < G::H; ++o) {
       orr[o] = ur[OUT + o] + wr[OUT + o];
       ori[o] = ui[OUT + o] + wi[OUT + o];
     }
-    hop_terms<T, Q, L, LD, C, 1, true>(ln, orr, ori, Sr, Si);
   }
+  apply_half<T, Q, L, LD, C, HOP>(ln, cf, vr, vi, Sr, Si, orr, ori);
 #pragma unroll
   for (int o = 0; o < G::H; ++o)
     jacobi_update<T, Q, L, LD, REV>(ln, OUT + o, Sr[o], Si[o], xr[OUT + o], xi[OUT + o], wr[OUT + o], wi[OUT + o]);
@@ -811,14 +833,8 @@ __device__ __forceinline__ void half_sweep2(const Lane<T, Q, L, LD> &ln, const C
     rr[G::H + o] = vbr[IN + o];
     ri[G::H + o] = vbi[IN + o];
   }
-  T n[2 * (LD > 0 ? LD : 1)][4 * G::H];
-  lane_exchange<T, Q, L, LD, 2 * G::H>(ln, rr, ri, n);
-  T Sr[2 * G::H], Si[2 * G::H];
-  apply_half_regs<T, Q, L, LD, C>(ln, cf, var, vai, Sr, Si);
-  apply_half_regs<T, Q, L, LD, C>(ln, cf, vbr, vbi, Sr + G::H, Si + G::H);
-  lane_digit_terms<T, Q, L, LD, 2 * G::H>(ln, cf.lor, cf.loi, cf.hir, cf.hii, n, Sr, Si);
+  T orr[2 * G::H], ori[2 * G::H];         // HOP: own-colour values, sent in the same exchange
   if constexpr (HOP) {
-    T orr[2 * G::H], ori[2 * G::H];
 #pragma unroll
     for (int o = 0; o < G::H; ++o) {
       orr[o] = uar[OUT + o] + war[OUT + o];
@@ -826,8 +842,14 @@ __device__ __forceinline__ void half_sweep2(const Lane<T, Q, L, LD> &ln, const C
       orr[G::H + o] = ubr[OUT + o] + wbr[OUT + o];
       ori[G::H + o] = ubi[OUT + o] + wbi[OUT + o];
     }
-    hop_terms<T, Q, L, LD, C, 2, true>(ln, orr, ori, Sr, Si);
   }
+  T n[2 * (LD > 0 ? LD : 1)][4 * G::H];
+  lane_exchange<T, Q, L, LD, 2 * G::H, HOP ? 2 * G::H : 0>(ln, rr, ri, n, orr, ori);
+  T Sr[2 * G::H], Si[2 * G::H];
+  apply_half_regs<T, Q, L, LD, C>(ln, cf, var, vai, Sr, Si);
+  apply_half_regs<T, Q, L, LD, C>(ln, cf, vbr, vbi, Sr + G::H, Si + G::H);
+  lane_digit_terms<T, Q, L, LD, 2 * G::H>(ln, cf.lor, cf.loi, cf.hir, cf.hii, n, Sr, Si);
+  if constexpr (HOP) hop_terms<T, Q, L, LD, C, 2>(ln, ln.xb + xtail<T, 2 * G::H>(), orr, ori, Sr, Si);
 #pragma unroll
   for (int o = 0; o < G::H; ++o) {
     jacobi_update<T, Q, L, LD, REV>(ln, OUT + o, Sr[o], Si[o], xar[OUT + o], xai[OUT + o], war[OUT + o], wai[OUT + o]);
@@ -934,7 +956,17 @@ __device__ __forceinline__ void forward_item(const DevSys &s, int m, int cg, dou
   int next_boundary = 1;
   int since = 0, icp = 0;              // steps since the last checkpoint, checkpoints written
 
+  typename C2<T>::type cnext[Q];
+  if constexpr (ctrl_ahead<G>()) load_ctrl<T, Q>(ctrl, k0, cnext);
   for (long long k = k0; k < k1; ++k) {
+    typename C2<T>::type ccur[Q];
+    if constexpr (ctrl_ahead<G>()) {
+#pragma unroll
+      for (int j = 0; j < Q; ++j) ccur[j] = cnext[j];
+      load_ctrl<T, Q>(ctrl, k + 1 < k1 ? k + 1 : k, cnext);
+    } else {
+      load_ctrl<T, Q>(ctrl, k, ccur);
+    }
     if (!ROLLOUT && s.ckpt_every > 0 && since == s.ckpt_every) {   // U_{k0 + (icp+1) C}
       double2 *cp = reinterpret_cast<double2 *>(s.ckpt) + (((size_t)m * s.ncp + icp) * s.E + ln.col) * s.N;
       if (ln.valid)
@@ -945,7 +977,7 @@ __device__ __forceinline__ void forward_item(const DevSys &s, int m, int cg, dou
     }
     ++since;
     Coef<T, Q, L, LD> cf;
-    step_coeffs<T, Q, L, LD>(ln, ctrl, k, cf);
+    step_coeffs<T, Q, L, LD>(ln, ccur, cf);
     T ur[G::EPL], ui[G::EPL], wr[G::EPL], wi[G::EPL];
 #pragma unroll
     for (int e = 0; e < G::EPL; ++e) {
@@ -979,8 +1011,8 @@ template <typename T, int Q, int L, int LD, bool ROLLOUT, bool HOP>
 __global__ __launch_bounds__(64) void k_forward(DevSys s, double *Wout, double *Uout, int nitems) {
   const int item = xcd_item(blockIdx.x, gridDim.x);
   if (item >= nitems) return;
-  __shared__ __align__(16) T xb[xchg_bytes<T>() / sizeof(T)];
-  xchg_clear(xb);
+  __shared__ __align__(16) T xb[xchg_bytes<T, HOP>() / sizeof(T)];
+  xchg_clear<T, HOP>(xb);
   if (ROLLOUT) forward_item<T, Q, L, LD, true, HOP>(s, 0, item, Wout, Uout, xb);
   else forward_item<T, Q, L, LD, false, HOP>(s, item / s.ncg, item % s.ncg, nullptr, nullptr, xb);
 }
@@ -1198,9 +1230,19 @@ __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T 
     ic = (int)(k1 - 1 - k0) / s.ckpt_every;
   }
 
+  typename C2<T>::type cnext[Q];
+  if constexpr (ctrl_ahead<G>()) load_ctrl<T, Q>(ctrl, k1 - 1, cnext);
   for (long long k = k1 - 1; k >= k0; --k) {
+    typename C2<T>::type ccur[Q];
+    if constexpr (ctrl_ahead<G>()) {
+#pragma unroll
+      for (int j = 0; j < Q; ++j) ccur[j] = cnext[j];
+      load_ctrl<T, Q>(ctrl, k > k0 ? k - 1 : k, cnext);
+    } else {
+      load_ctrl<T, Q>(ctrl, k, ccur);
+    }
     Coef<T, Q, L, LD> cf;
-    step_coeffs<T, Q, L, LD>(ln, ctrl, k, cf);
+    step_coeffs<T, Q, L, LD>(ln, ccur, cf);
     T ur[G::EPL], ui[G::EPL], lr[G::EPL], li[G::EPL];
     T wur[G::EPL], wui[G::EPL], wlr[G::EPL], wli[G::EPL];
 #pragma unroll
@@ -1279,13 +1321,16 @@ __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T 
   for (int e = 0; e < G::EPL; ++e) l0[ln.row(e)] = double2{ldr[e], ldi[e]};
 }
 
+// The FP32 dipole variant is held to two waves per SIMD (it would otherwise exceed
+// the 256-register budget by a few registers and run at one).
 template <typename T, int Q, int L, int LD, bool HOP>
-__global__ __launch_bounds__(64) void k_backward(DevSys s, int nitems) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HOP && sizeof(T) == 4 ? 2 : 1)))
+void k_backward(DevSys s, int nitems) {
   const int item = xcd_item(blockIdx.x, gridDim.x);
   if (item >= nitems) return;
   __shared__ T red[red_elems<T>()];
-  __shared__ __align__(16) T xb[xchg_bytes<T>() / sizeof(T)];
-  xchg_clear(xb);
+  __shared__ __align__(16) T xb[xchg_bytes<T, HOP>() / sizeof(T)];
+  xchg_clear<T, HOP>(xb);
   backward_item<T, Q, L, LD, HOP>(s, item / s.ncg, item % s.ncg, red, xb);
 }
 
@@ -1581,8 +1626,8 @@ bool lookup(int q, int L, bool hop, Kernels *k, int *ld, int *cpw, int *shape) {
 // items ordered by the host (longest first).
 template <typename T>
 __global__ __launch_bounds__(64) void k_forward_batch(const DevSys *sys, const int4 *items) {
-  __shared__ __align__(16) T xb[xchg_bytes<T>() / sizeof(T)];
-  xchg_clear(xb);
+  __shared__ __align__(16) T xb[xchg_bytes<T, true>() / sizeof(T)];   // either variant
+  xchg_clear<T, true>(xb);
   const int4 it = items[blockIdx.x];
   const DevSys s = sys[it.x];
   switch (it.w) {
@@ -1600,8 +1645,8 @@ __global__ __launch_bounds__(64) void k_forward_batch(const DevSys *sys, const i
 template <typename T>
 __global__ __launch_bounds__(64) void k_backward_batch(const DevSys *sys, const int4 *items) {
   __shared__ T red[red_elems<T>()];
-  __shared__ __align__(16) T xb[xchg_bytes<T>() / sizeof(T)];
-  xchg_clear(xb);
+  __shared__ __align__(16) T xb[xchg_bytes<T, true>() / sizeof(T)];   // either variant
+  xchg_clear<T, true>(xb);
   const int4 it = items[blockIdx.x];
   const DevSys s = sys[it.x];
   switch (it.w) {
