@@ -1594,13 +1594,16 @@ Kernels make() {
 }
 
 // (q, L) -> lane digits, chosen so that each lane holds at most four entries
-// per state (the backward sweep keeps about 16 such arrays live).
+// per state (the backward sweep keeps about 16 such arrays live).  Two-level
+// systems use two entries per lane: their windows are latency-bound chains (few
+// wavefronts, several columns each), and halving a lane's entries halves its
+// instructions per step.
 #define QOC_SHAPES(X)   \
   X(1, 2, 0) X(1, 3, 0) X(1, 4, 0) \
-  X(2, 2, 0) X(2, 3, 1) X(2, 4, 1) \
-  X(3, 2, 1) X(3, 3, 2) X(3, 4, 2) \
-  X(4, 2, 2) X(4, 3, 3) X(4, 4, 3) \
-  X(5, 2, 3) X(6, 2, 4)
+  X(2, 2, 1) X(2, 3, 1) X(2, 4, 1) \
+  X(3, 2, 2) X(3, 3, 2) X(3, 4, 2) \
+  X(4, 2, 3) X(4, 3, 3) X(4, 4, 3) \
+  X(5, 2, 4) X(6, 2, 5)
 
 // Kernel-instance index: the shape, plus N_SHAPES for the dipole variant.
 #define X(Q_, L_, LD_) SHAPE_##Q_##_##L_,
