@@ -277,6 +277,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU-oracle sample size (0: skip)")
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--no-extras", action="store_true", help="skip the batched-mix, serving, dipole and optimisation measurements")
+    ap.add_argument("--extras", default="batch,serve,dipole,opt",
+                    help="which extra measurements to run (comma-separated subset of batch,serve,dipole,opt)")
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-plain-requests", type=int, default=600)
@@ -406,28 +408,30 @@ def main():
         s64.close()
         log(f"fp64 plain form: {args.fp64_steps / e64:.2f} evals/s")
 
-    if not args.no_extras:
+    extras = set() if args.no_extras else {e for e in args.extras.split(",") if e}
+    if extras & {"batch", "serve"}:
         try:
             result["batched_mix"] = bench_batch(args.seed, args.batch_reps, log)
-            rate = args.serve_load * result["batched_mix"]["evals_per_s"]
-            result["serving"] = bench_serve(rate, args.serve_requests, args.serve_plain_requests, args.seed,
-                                            args.hbm_budget_gb, log)
+            if "serve" in extras:
+                rate = args.serve_load * result["batched_mix"]["evals_per_s"]
+                result["serving"] = bench_serve(rate, args.serve_requests, args.serve_plain_requests, args.seed,
+                                                args.hbm_budget_gb, log)
         except Exception as e:   # the headline line must still be printed
             result["extras_error"] = repr(e)
             log(f"extras failed: {e!r}")
-        if args.dipole_steps > 0:
-            try:
-                result["dipole"] = bench_dipole(args.dipole_steps, 5, args.seed, log)
-            except Exception as e:
-                result["dipole_error"] = repr(e)
-                log(f"dipole systems failed: {e!r}")
-        runs = [tuple(int(x) for x in r.split(":")) for r in args.opt_runs.split(",") if r]
-        if runs:
-            try:
-                result["optimisation"] = bench_optimize(runs, args.seed, log, args.opt_seconds)
-            except Exception as e:
-                result["optimisation_error"] = repr(e)
-                log(f"optimisation failed: {e!r}")
+    if "dipole" in extras and args.dipole_steps > 0:
+        try:
+            result["dipole"] = bench_dipole(args.dipole_steps, 5, args.seed, log)
+        except Exception as e:
+            result["dipole_error"] = repr(e)
+            log(f"dipole systems failed: {e!r}")
+    runs = [tuple(int(x) for x in r.split(":")) for r in args.opt_runs.split(",") if r]
+    if "opt" in extras and runs:
+        try:
+            result["optimisation"] = bench_optimize(runs, args.seed, log, args.opt_seconds)
+        except Exception as e:
+            result["optimisation_error"] = repr(e)
+            log(f"optimisation failed: {e!r}")
 
     if args.cpu_seconds > 0:
         result["cpu_baseline"] = cpu_baseline(w, alpha_np, args.cpu_seconds)
