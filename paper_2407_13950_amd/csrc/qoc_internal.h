@@ -91,6 +91,10 @@ int launch_batch_phase(const BatchPlan &p, int phase, hipStream_t st);
 // block in a fixed order; results land in device memory.  All return 0 or a hipError_t.
 constexpr int kOptGrid = 512;
 int opt_dot(const double *a, const double *b, long long n, double *partials, double *out, hipStream_t st);
+// out[0] = cb * base[0] + cs * (a . b) (base may be NULL: out[0] = cs * (a . b)), all on the device
+int opt_dot_to(const double *a, const double *b, long long n, double *partials, double *out, double cs,
+               const double *base, double cb, hipStream_t st);
+int opt_axpy_dev(double *y, const double *c, double s, const double *x, long long n, hipStream_t st);  // y += s c[0] x
 int opt_maxabs(const double *v, long long n, double *partials, double *out, hipStream_t st);
 int opt_axpby(double *y, double a, const double *x, double b, long long n, hipStream_t st);       // y = a x + b y
 int opt_trial(double *xt, const double *x, const double *p, double t, long long n, long long d, double lo, double hi,

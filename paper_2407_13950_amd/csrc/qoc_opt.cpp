@@ -3,8 +3,10 @@
 // control-energy terms, window states scaled by sigma, roll-out-estimate stopping
 // rule of eq. rollout-infid-est).  It calls the objective/gradient ABI of the
 // context it owns; the optimisation vectors (about 1e6 doubles at 4 qubits) and
-// the L-BFGS history stay in device memory, and only scalars reach the host.
-// The iteration is specified in include/qoc.h.
+// the L-BFGS history stay in device memory, and only scalars reach the host.  The
+// two-loop recursion keeps its coefficients on the device, so an iteration waits
+// for the device three times: for (|gr|_inf, g.p), once per trial point, and for
+// the curvature pair.  The iteration is specified in include/qoc.h.
 #include "../../include/qoc.h"
 #include "qoc_internal.h"
 
@@ -47,7 +49,10 @@ struct qoc_opt {
   // device vectors
   double *x = nullptr, *g = nullptr, *xt = nullptr, *gt = nullptr, *p = nullptr, *q = nullptr, *gr = nullptr,
          *ytmp = nullptr, *Wbuf = nullptr, *ga = nullptr, *gW = nullptr, *gE = nullptr, *dtab = nullptr,
-         *partials = nullptr, *res = nullptr;
+         *partials = nullptr, *res = nullptr, *acoef = nullptr, *bcoef = nullptr;
+  // device scalars in res: [0..kObj) single values, then P and the 4 + M terms
+  enum { R_GINF = 0, R_GP, R_GG, R_GS, R_EN, R_AA, R_SY, R_YY, R_SS, kObj = 12 };
+  std::vector<double> hres;             // host copy of res
   std::vector<double *> S, Y;
   std::vector<double> rho, sy, yy;      // per history slot
   int hist = 0, newest = -1;            // pairs kept; slot of the newest (ring of D.memory slots)
@@ -71,15 +76,19 @@ struct qoc_opt {
     *ptr = static_cast<double *>(v);
     return QOC_OK;
   }
-  // device scalars -> host (waits for the stream)
-  int fetch(double *h, int count) {
-    HIPCHK(hipMemcpyAsync(h, res, sizeof(double) * count, hipMemcpyDeviceToHost, st));
+  // res[0..count) -> hres (waits for the stream); also reports a fixed-point bound
+  // violation flagged by the evaluations queued since the last wait
+  int fetch(int count) {
+    int status[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(hres.data(), res, sizeof(double) * count, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(status, qoc::ctx_dev(ctx).status, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    if (status[0] & qoc::STATUS_NOTCONV) return qoc_synchronize(ctx);   // clears the flag, returns QOC_ENOTCONV
     return QOC_OK;
   }
-  int dot(const double *a, const double *b, long long len, double *out) {
-    HIPCHK(qoc::opt_dot(a, b, len, partials, res, st));
-    return fetch(out, 1);
+  int dot(const double *a, const double *b, long long len, int slot) {
+    HIPCHK(qoc::opt_dot(a, b, len, partials, res + slot, st));
+    return QOC_OK;
   }
   double estimate(const Point &pt) const {
     const double J = pt.terms[0];
@@ -87,20 +96,22 @@ struct qoc_opt {
     for (int m = 0; m + 1 < M; ++m) csum += std::sqrt(std::max(pt.terms[5 + m], 0.0));
     return J + 2.0 / std::sqrt((double)E) * std::sqrt(std::max(J, 0.0)) * csum + csum * csum / E;
   }
-  // F at v (device vector): sets the context's inputs from v, objective, energy, Tikhonov
+  // F at v (device vector): sets the context's inputs from v, objective, energy,
+  // Tikhonov; one wait, which also returns the scalars the caller queued before
   int eval_objective(const double *v, Point &pt) {
     QOCCHK(qoc_set_controls(ctx, v, d, QOC_DEVICE));
     if (M > 1) {
       HIPCHK(qoc::opt_axpby(Wbuf, 1.0 / D.sigma, v + d, 0.0, nW, st));
       QOCCHK(qoc_set_window_states(ctx, Wbuf, nW, QOC_DEVICE));
     }
-    QOCCHK(qoc_objective(ctx, &pt.P, pt.terms.data(), QOC_HOST));
-    HIPCHK(qoc::opt_energy(qoc::ctx_dev(ctx), v, dtab, partials, res, st));
-    HIPCHK(qoc::opt_dot(v, v, d, partials, res + 1, st));
-    double h[2];
-    QOCCHK(fetch(h, 2));
-    pt.energy = dt * h[0];
-    pt.tik = 0.5 * D.gamma_tik * h[1];
+    HIPCHK(qoc::opt_energy(qoc::ctx_dev(ctx), v, dtab, partials, res + R_EN, st));
+    QOCCHK(dot(v, v, d, R_AA));
+    QOCCHK(qoc_objective(ctx, res + kObj, res + kObj + 1, QOC_DEVICE));
+    QOCCHK(fetch(kObj + 5 + M));
+    pt.P = hres[kObj];
+    std::copy(hres.begin() + kObj + 1, hres.begin() + kObj + 5 + M, pt.terms.begin());
+    pt.energy = dt * hres[R_EN];
+    pt.tik = 0.5 * D.gamma_tik * hres[R_AA];
     pt.F = pt.P + pt.tik + D.gamma_energy * pt.energy;
     ++evals;
     return QOC_OK;
@@ -122,59 +133,51 @@ struct qoc_opt {
 
 int qoc_opt::iterate() {
   QOCCHK(reduced(gr, g));
-  HIPCHK(qoc::opt_maxabs(gr, n, partials, res, st));
-  QOCCHK(fetch(&grad_inf, 1));
-  if (estimate(cur) < D.tol_estimate) { stop = 1; return QOC_OK; }
-  if (D.tol_grad > 0.0 && grad_inf < D.tol_grad) { stop = 2; return QOC_OK; }
+  HIPCHK(qoc::opt_maxabs(gr, n, partials, res + R_GINF, st));
 
-  // p = -H gr (two-loop recursion), restricted to the free entries
+  // p = -H gr (two-loop recursion, coefficients on the device), restricted to the free entries
   bool used_hist = hist > 0;
   HIPCHK(qoc::opt_axpby(q, 1.0, gr, 0.0, n, st));
   if (used_hist) {
     const int m = D.memory;
-    std::vector<double> a(m, 0.0);
-    for (int i = 0; i < hist; ++i) {                      // newest to oldest
+    for (int i = 0; i < hist; ++i) {                      // newest to oldest: a = rho s.q, q -= a y
       const int sl = (newest - i + m) % m;
-      double sq;
-      QOCCHK(dot(S[sl], q, n, &sq));
-      a[sl] = rho[sl] * sq;
-      HIPCHK(qoc::opt_axpby(q, -a[sl], Y[sl], 1.0, n, st));
+      HIPCHK(qoc::opt_dot_to(S[sl], q, n, partials, acoef + sl, rho[sl], nullptr, 0.0, st));
+      HIPCHK(qoc::opt_axpy_dev(q, acoef + sl, -1.0, Y[sl], n, st));
     }
     HIPCHK(qoc::opt_axpby(q, 0.0, q, sy[newest] / yy[newest], n, st));
-    for (int i = hist - 1; i >= 0; --i) {                 // oldest to newest
+    for (int i = hist - 1; i >= 0; --i) {                 // oldest to newest: q += (a - rho y.q) s
       const int sl = (newest - i + m) % m;
-      double yq;
-      QOCCHK(dot(Y[sl], q, n, &yq));
-      HIPCHK(qoc::opt_axpby(q, a[sl] - rho[sl] * yq, S[sl], 1.0, n, st));
+      HIPCHK(qoc::opt_dot_to(Y[sl], q, n, partials, bcoef + sl, -rho[sl], acoef + sl, 1.0, st));
+      HIPCHK(qoc::opt_axpy_dev(q, bcoef + sl, 1.0, S[sl], n, st));
     }
   }
   HIPCHK(qoc::opt_axpby(p, -1.0, q, 0.0, n, st));
   QOCCHK(reduced(p, p));
-  double gp;
-  QOCCHK(dot(g, p, n, &gp));
-  if (!(gp < 0.0)) {                                       // not a descent direction: restart
+  QOCCHK(dot(g, p, n, R_GP));
+  QOCCHK(dot(gr, gr, n, R_GG));
+  QOCCHK(fetch(R_GG + 1));
+  grad_inf = hres[R_GINF];
+  if (estimate(cur) < D.tol_estimate) { stop = 1; return QOC_OK; }
+  if (D.tol_grad > 0.0 && grad_inf < D.tol_grad) { stop = 2; return QOC_OK; }
+  if (!(hres[R_GP] < 0.0)) {                               // not a descent direction: restart
     hist = 0;
     newest = -1;
     used_hist = false;
     HIPCHK(qoc::opt_axpby(p, -1.0, gr, 0.0, n, st));
   }
   double t = 1.0;
-  if (!used_hist) {
-    double gg;
-    QOCCHK(dot(gr, gr, n, &gg));
-    t = 1.0 / std::max(1.0, std::sqrt(gg));
-  }
+  if (!used_hist) t = 1.0 / std::max(1.0, std::sqrt(hres[R_GG]));
 
   // backtracking on the projected step
   bool accepted = false;
   for (int h = 0; h < kMaxHalvings; ++h) {
     HIPCHK(qoc::opt_trial(xt, x, p, t, n, d, -amax, amax, st));
-    QOCCHK(eval_objective(xt, trial));
     HIPCHK(qoc::opt_axpby(q, 1.0, xt, 0.0, n, st));       // s = xt - x
     HIPCHK(qoc::opt_axpby(q, -1.0, x, 1.0, n, st));
-    double gs;
-    QOCCHK(dot(g, q, n, &gs));
-    if (trial.F <= cur.F + kArmijo * gs) {
+    QOCCHK(dot(g, q, n, R_GS));
+    QOCCHK(eval_objective(xt, trial));                     // (returns g.s with the objective)
+    if (trial.F <= cur.F + kArmijo * hres[R_GS]) {
       accepted = true;
       break;
     }
@@ -190,10 +193,11 @@ int qoc_opt::iterate() {
   // curvature pair (s, y) = (xt - x, gt - g)
   HIPCHK(qoc::opt_axpby(ytmp, 1.0, gt, 0.0, n, st));
   HIPCHK(qoc::opt_axpby(ytmp, -1.0, g, 1.0, n, st));
-  double s_y, y_y, s_s;
-  QOCCHK(dot(q, ytmp, n, &s_y));
-  QOCCHK(dot(ytmp, ytmp, n, &y_y));
-  QOCCHK(dot(q, q, n, &s_s));
+  QOCCHK(dot(q, ytmp, n, R_SY));
+  QOCCHK(dot(ytmp, ytmp, n, R_YY));
+  QOCCHK(dot(q, q, n, R_SS));
+  QOCCHK(fetch(R_SS + 1));
+  const double s_y = hres[R_SY], y_y = hres[R_YY], s_s = hres[R_SS];
   if (s_y > kCurvature * std::sqrt(s_s * y_y)) {
     const int m = D.memory;
     const int sl = (newest + 1) % m;
@@ -255,7 +259,10 @@ int qoc_opt_create(qoc_ctx *ctx, const qoc_opt_desc *desc, const double *alpha0,
   QOCCHK(o->alloc(&o->gE, o->d));
   QOCCHK(o->alloc(&o->dtab, (size_t)2 * sys.NT * sys.q));
   QOCCHK(o->alloc(&o->partials, std::max(qoc::kOptGrid, qoc::opt_energy_blocks(sys))));
-  QOCCHK(o->alloc(&o->res, 8));
+  QOCCHK(o->alloc(&o->res, qoc_opt::kObj + 5 + o->M));
+  QOCCHK(o->alloc(&o->acoef, Dd.memory));
+  QOCCHK(o->alloc(&o->bcoef, Dd.memory));
+  o->hres.assign(qoc_opt::kObj + 5 + o->M, 0.0);
   o->S.resize(Dd.memory);
   o->Y.resize(Dd.memory);
   for (int i = 0; i < Dd.memory; ++i) {
@@ -302,8 +309,9 @@ int qoc_opt_run(qoc_opt *opt, int32_t n_iters, qoc_opt_status *status) {
   for (int i = 0; i < n_iters && opt->stop == 0; ++i) QOCCHK(opt->iterate());
   if (opt->stop == 0) {                                    // refresh |gr| and the stop test at the iterate
     QOCCHK(opt->reduced(opt->gr, opt->g));
-    HIPCHK(qoc::opt_maxabs(opt->gr, opt->n, opt->partials, opt->res, opt->st));
-    QOCCHK(opt->fetch(&opt->grad_inf, 1));
+    HIPCHK(qoc::opt_maxabs(opt->gr, opt->n, opt->partials, opt->res + qoc_opt::R_GINF, opt->st));
+    QOCCHK(opt->fetch(qoc_opt::R_GINF + 1));
+    opt->grad_inf = opt->hres[qoc_opt::R_GINF];
   }
   if (status) {
     qoc_opt_status &s = *status;

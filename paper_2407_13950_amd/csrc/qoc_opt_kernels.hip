@@ -54,20 +54,33 @@ __global__ __launch_bounds__(kThreads) void k_maxabs_partial(const double *v, lo
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-// out[0] = sum (or max) of partials[0..m) in a fixed tree order
+// out[0] = sum (or max) of partials[0..m) in a fixed tree order; for sums, optionally
+// combined with a device scalar: out[0] = cb * base[0] + cs * sum (base non-null).
 template <bool MAX>
-__global__ __launch_bounds__(kThreads) void k_finish(const double *partials, int m, double *out) {
+__global__ __launch_bounds__(kThreads) void k_finish(const double *partials, int m, double *out, const double *base,
+                                                     double cb, double cs) {
   __shared__ double sh[kThreads];
   double acc = 0.0;
   for (int i = threadIdx.x; i < m; i += kThreads) acc = MAX ? fmax(acc, partials[i]) : acc + partials[i];
   const double s = MAX ? block_reduce_max(acc, sh) : block_reduce_sum(acc, sh);
-  if (threadIdx.x == 0) out[0] = s;
+  if (threadIdx.x == 0) {
+    if (MAX || !base) out[0] = MAX ? s : cs * s;
+    else out[0] = cb * base[0] + cs * s;
+  }
 }
 
 // y = a x + b y
 __global__ __launch_bounds__(kThreads) void k_axpby(double *y, double a, const double *x, double b, long long n) {
   for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads)
     y[i] = fma(a, x[i], b * y[i]);
+}
+
+// y = (s c[0]) x + y with the coefficient c[0] in device memory
+__global__ __launch_bounds__(kThreads) void k_axpy_dev(double *y, const double *c, double s, const double *x,
+                                                       long long n) {
+  const double a = s * c[0];
+  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads)
+    y[i] = fma(a, x[i], y[i]);
 }
 
 // xt = x + t p, the first d entries clipped to [lo, hi]
@@ -176,14 +189,25 @@ int grid_for(long long n) {
 }  // namespace
 
 int opt_dot(const double *a, const double *b, long long n, double *partials, double *out, hipStream_t st) {
+  return opt_dot_to(a, b, n, partials, out, 1.0, nullptr, 0.0, st);
+}
+
+int opt_dot_to(const double *a, const double *b, long long n, double *partials, double *out, double cs,
+               const double *base, double cb, hipStream_t st) {
   hipLaunchKernelGGL(k_dot_partial, dim3(kOptGrid), dim3(kThreads), 0, st, a, b, n, partials);
-  hipLaunchKernelGGL(k_finish<false>, dim3(1), dim3(kThreads), 0, st, partials, kOptGrid, out);
+  hipLaunchKernelGGL(k_finish<false>, dim3(1), dim3(kThreads), 0, st, partials, kOptGrid, out, base, cb, cs);
   return (int)hipGetLastError();
 }
 
 int opt_maxabs(const double *v, long long n, double *partials, double *out, hipStream_t st) {
   hipLaunchKernelGGL(k_maxabs_partial, dim3(kOptGrid), dim3(kThreads), 0, st, v, n, partials);
-  hipLaunchKernelGGL(k_finish<true>, dim3(1), dim3(kThreads), 0, st, partials, kOptGrid, out);
+  hipLaunchKernelGGL(k_finish<true>, dim3(1), dim3(kThreads), 0, st, partials, kOptGrid, out, (const double *)nullptr,
+                     0.0, 1.0);
+  return (int)hipGetLastError();
+}
+
+int opt_axpy_dev(double *y, const double *c, double s, const double *x, long long n, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy_dev, dim3(grid_for(n)), dim3(kThreads), 0, st, y, c, s, x, n);
   return (int)hipGetLastError();
 }
 
@@ -216,7 +240,8 @@ int opt_energy_blocks(const DevSys &s) { return (int)((s.NT + kThreads - 1) / kT
 int opt_energy(const DevSys &s, const double *alpha, double *dtab, double *partials, double *out, hipStream_t st) {
   const int nb = opt_energy_blocks(s);
   hipLaunchKernelGGL(k_energy_table, dim3(nb), dim3(kThreads), 0, st, s, alpha, dtab, partials);
-  hipLaunchKernelGGL(k_finish<false>, dim3(1), dim3(kThreads), 0, st, partials, nb, out);
+  hipLaunchKernelGGL(k_finish<false>, dim3(1), dim3(kThreads), 0, st, partials, nb, out, (const double *)nullptr, 0.0,
+                     1.0);
   return (int)hipGetLastError();
 }
 
