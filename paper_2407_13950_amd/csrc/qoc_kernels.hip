@@ -208,7 +208,6 @@ struct Lane {
   // sqrt(l_j + 1) sqrt(l_{j+1})), term B the row with l_j - 1, l_{j+1} + 1 (weight
   // sqrt(l_j) sqrt(l_{j+1} + 1)), both zero off the ends of the digits.
   static constexpr int NPL = LD > 1 ? LD - 1 : 1;
-  T hc[Q];                      // (dt/2) J_j
   T hla[NPL], hlb[NPL];         // lane-digit pairs (R+jj, R+jj+1): full A and B weights
   T hsa, hsb;                   // pair (R-1, R): (dt/2) J_{R-1} sqrt(l_R), (dt/2) J_{R-1} sqrt(l_R + 1)
 
@@ -252,8 +251,6 @@ struct Lane {
     int l[LD > 0 ? LD : 1];
 #pragma unroll
     for (int jj = 0; jj < LD; ++jj) l[jj] = valid ? (sub / G::lstride(jj)) % L : 0;
-#pragma unroll
-    for (int j = 0; j < Q; ++j) hc[j] = (T)(j + 1 < Q ? s.hop_c[j] : 0.0);
 #pragma unroll
     for (int jj = 0; jj < NPL; ++jj) {
       hla[jj] = hlb[jj] = (T)0;
@@ -382,17 +379,17 @@ __device__ __forceinline__ void lane_digit_terms(const Lane<T, Q, L, LD> &ln, co
 // on NO output slots for NRHS right-hand sides.  The exchange keeps the digit sum,
 // so in the red-black layout (C >= 0) an output slot of colour C reads the current
 // values of colour C; the caller passes them, own[b*NO + o] with o the slot within
-// the colour (C < 0: plain layout, all EPL slots).  Register digits: only the pair
-// (leading digit, next register digit) occurs (R <= 2).  Lane digits read the other
+// the colour (C < 0: plain layout, all EPL slots).  The layouts keep one register
+// digit (R = 1), so every pair has a lane digit.  Lane digits read the other
 // lanes' own-colour values from the records at `base`, written by the caller's lane
 // exchange (red-black: a second record behind the ladder's; plain layout: the
 // ladder's record itself).  Every read of a value that lies outside the digit range
 // meets a zero weight.
 
-// Red-black output slot (s0, t) of colour C: source slot of the pair (l0 +- 1, l' -+ 1)
-// when l0 and one other digit change together (same lane and leading+register pair, or
-// leading digit with the neighbouring lane): the source has the other lead parity, so
-// A (l0 + 1) sits at s0 + b and B (l0 - 1) at s0 - 1 + b, b the output's lead parity.
+// Red-black output slot s0 of colour C, pair (register digit, first lane digit): the
+// source row (l0 +- 1, lane digit -+ 1) sits in the neighbouring lane, whose lead
+// parity is the other one, so A (l0 + 1) is its slot s0 + b and B (l0 - 1) its slot
+// s0 - 1 + b, b the output's lead parity.
 template <int HALF>
 __device__ __forceinline__ constexpr int lead_up(int s0, int b) { return s0 + b < HALF ? s0 + b : s0; }
 template <int HALF>
@@ -428,39 +425,10 @@ __device__ __forceinline__ void hop_terms(const Lane<T, Q, L, LD> &ln, const T *
   constexpr int NV = 2 * NO * NRHS;
   constexpr int R = G::R;
   static_assert(!RBL || G::RB, "a colour needs the red-black layout");
-  static_assert(RBL ? R <= 2 : R <= 1, "exchange pairs of two register digits other than the leading pair");
-  // register pair (0, 1), red-black with R = 2: the leading digit l0 and digit 1 (t's only digit)
-  if constexpr (RBL && R == 2 && Q >= 2) {
-#pragma unroll
-    for (int o = 0; o < NO; ++o) {
-      const int s0 = o / G::RT, t = o % G::RT;
-      const int beta = G::tpar(t) ^ C;
-      const int bl = ln.par ^ beta;
-      const int l1 = t % L;                     // digit 1 (stride 1 within t)
-#pragma unroll
-      for (int b = 0; b < NRHS; ++b) {
-        if (l1 > 0) {                           // A: l0 + 1, l1 - 1
-          const int ta = t - 1;
-          const int i0 = b * NO + s0 * G::RT + ta, i1 = b * NO + lead_up<G::HALF>(s0, 1) * G::RT + ta;
-          const T vr = bl ? ownr[i1] : ownr[i0], vi = bl ? owni[i1] : owni[i0];
-          const T w = ln.hc[0] * (T)sqrt((double)l1) * ln.wup[beta][s0];
-          Sr[b * NO + o] = fma_(w, vr, Sr[b * NO + o]);
-          Si[b * NO + o] = fma_(w, vi, Si[b * NO + o]);
-        }
-        if (l1 < L - 1) {                       // B: l0 - 1, l1 + 1
-          const int tb = t + 1;
-          const int i0 = b * NO + lead_dn<G::HALF>(s0, 0) * G::RT + tb, i1 = b * NO + s0 * G::RT + tb;
-          const T vr = bl ? ownr[i1] : ownr[i0], vi = bl ? owni[i1] : owni[i0];
-          const T w = ln.hc[0] * (T)sqrt((double)(l1 + 1)) * ln.wdn[beta][s0];
-          Sr[b * NO + o] = fma_(w, vr, Sr[b * NO + o]);
-          Si[b * NO + o] = fma_(w, vi, Si[b * NO + o]);
-        }
-      }
-    }
-  }
+  static_assert(R == 1 || Q < 2, "every layout keeps one register digit: no pair of two register digits");
   if constexpr (LD > 0) {
-    // pair (R-1, R): register digit R-1 and lane digit 0.  A reads the lane one step
-    // down in lane digit 0 (l_R - 1), B the lane one step up.
+    // pair (0, 1): the register digit and lane digit 0.  A reads the lane one step
+    // down in lane digit 0 (l_1 - 1), B the lane one step up.
     {
       constexpr int ST = G::lstride(0);
       T dn[NV], up[NV];
@@ -471,7 +439,7 @@ __device__ __forceinline__ void hop_terms(const Lane<T, Q, L, LD> &ln, const T *
 #pragma unroll
         for (int b = 0; b < NRHS; ++b) {
           const int so = b * NO + o;
-          if constexpr (RBL && R == 1) {        // digit R-1 is the leading digit
+          if constexpr (RBL) {                  // l0 = 2 s0 + (lead parity)
             const int s0 = o;                   // RT = 1
             const int beta = C;
             const int bl = ln.par ^ beta;
@@ -484,18 +452,16 @@ __device__ __forceinline__ void hop_terms(const Lane<T, Q, L, LD> &ln, const T *
             Si[so] = fma_(wa, ai, Si[so]);
             Sr[so] = fma_(wb, br, Sr[so]);
             Si[so] = fma_(wb, bi, Si[so]);
-          } else {
-            // digit R-1 known at compile time: in t (red-black, R = 2) or in e (plain layout, R = 1)
-            const int la = RBL ? (o % G::RT) % L : G::rdigit(o, R - 1);
-            constexpr int DS = RBL ? 1 : G::rstride(R - 1);
+          } else {                              // plain layout: slot o holds register digit o
+            const int la = o;
             if (la < L - 1) {
-              const int src = b * NO + o + DS;
+              const int src = b * NO + o + 1;
               const T w = ln.hsa * (T)sqrt((double)(la + 1));
               Sr[so] = fma_(w, dn[2 * src], Sr[so]);
               Si[so] = fma_(w, dn[2 * src + 1], Si[so]);
             }
             if (la > 0) {
-              const int src = b * NO + o - DS;
+              const int src = b * NO + o - 1;
               const T w = ln.hsb * (T)sqrt((double)la);
               Sr[so] = fma_(w, up[2 * src], Sr[so]);
               Si[so] = fma_(w, up[2 * src + 1], Si[so]);

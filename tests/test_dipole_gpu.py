@@ -178,3 +178,50 @@ def test_optimizer_on_paper_qft4_follows_the_oracle():
     W0 = Wr + WL.gen_noise(w, 3, std=1e-2)
     st = TO.compare_run(w, alpha0, W0, pr, "fp64", iters=6, tol_F=1e-10, tol_x=1e-8)
     assert np.isfinite(st["F"])
+
+
+def expected_count(w, alpha, prec):
+    """The fixed-point count from its definition, computed independently of the library: the
+    contraction bound rho = max_k nu_L sum_j (dt/2)|c_j(t_{k+1/2})| (nu_L = |a + a^+|_2, eigvalsh),
+    beta = (dt/2) sum_j |J_j| |a^+ b + a b^+|_2, and the smallest count whose error bound meets the
+    solve tolerance (Jacobi: (rho+beta)^(K+1); red-black: the per-colour recursion)."""
+    L, dt = w.L, w.T / w.n_steps
+    a = np.diag(np.sqrt(np.arange(1.0, L)), 1)
+    nu_L = float(np.linalg.eigvalsh(a + a.T).max())
+    nu_X = float(np.abs(np.linalg.eigvalsh(np.kron(a.T, a) + np.kron(a, a.T))).max())
+    rho = 0.0
+    for k in range(w.n_steps):
+        c = O.controls(w, alpha, (k + 0.5) * dt)
+        rho = max(rho, float(np.float32(0.5 * dt * float(np.sum(np.abs(c))) * nu_L)))
+    rho *= 1.0 + 1e-6
+    beta = 0.5 * dt * float(np.sum(np.abs(w.dipole_or_zero))) * nu_X
+    tol = 2.0 ** (-54 if prec == "fp64" else -26)
+    tau = rho + beta
+    if L % 2:
+        K, err = 1, tau * tau
+        while err > tol and K < 64:
+            err *= tau
+            K += 1
+        return K
+    x0 = x1 = tau
+    x0 = rho * x1 + beta * x0
+    K, err = 1, math.hypot(x0, x1)
+    while err > tol and K < 64:
+        K += 1
+        if K % 2:
+            x0 = rho * x1 + beta * x0
+        else:
+            x1 = rho * x0 + beta * x1
+        err = math.hypot(x0, x1)
+    return K
+
+
+@pytest.mark.parametrize("q,L,dip", [(3, 4, False), (3, 4, True), (2, 3, False), (2, 3, True), (3, 2, True)])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_count_matches_its_definition(q, L, dip, prec):
+    w, alpha, W = dipole_case(q, L, 240, 4) if dip else PG.small_case(q, L, 240, 4)
+    alpha = 3.0 * alpha                                   # stronger controls: several counts apart
+    k = bound_count(w, alpha, W, prec)
+    want = expected_count(w, alpha, prec)
+    print(f"{w.name} {prec}: count {k} (definition {want})", flush=True)
+    assert k == want
