@@ -31,6 +31,9 @@
 // see Geo): H_c only couples rows of opposite digit-sum parity, so the solve
 // refreshes one colour at a time from the other's newest values, which reaches the
 // Jacobi error bound of K iterations in K+1 half sweeps of half the work each.
+// The optional dipole exchange of the chain (eq. sys-ham) joins the iteration in
+// a second instance of every sweep kernel (HOP): it keeps the digit-sum parity, so
+// a colour takes it from its own current values.
 #include "qoc_internal.h"
 
 #include <cmath>
@@ -378,13 +381,12 @@ __device__ __forceinline__ void lane_digit_terms(const Lane<T, Q, L, LD> &ln, co
 // S += (dt/2) H_J v, H_J = sum_j J_j (a_{j+1}^+ a_j + a_{j+1} a_j^+) (eq. sys-ham, chain),
 // on NO output slots for NRHS right-hand sides.  The exchange keeps the digit sum,
 // so in the red-black layout (C >= 0) an output slot of colour C reads the current
-// values of colour C; the caller passes them, own[b*NO + o] with o the slot within
-// the colour (C < 0: plain layout, all EPL slots).  The layouts keep one register
-// digit (R = 1), so every pair has a lane digit.  Lane digits read the other
-// lanes' own-colour values from the records at `base`, written by the caller's lane
-// exchange (red-black: a second record behind the ladder's; plain layout: the
-// ladder's record itself).  Every read of a value that lies outside the digit range
-// meets a zero weight.
+// values of colour C (C < 0: plain layout, all EPL slots).  The layouts keep one
+// register digit (R = 1), so every pair involves a lane digit and every source value
+// comes from another lane: from the records at `base`, written by the caller's lane
+// exchange (red-black: the own-colour values, record[b*NO + o], o the slot within the
+// colour, sent behind the ladder's record; plain layout: the ladder's record itself).
+// Every read of a value that lies outside the digit range meets a zero weight.
 
 // Red-black output slot s0 of colour C, pair (register digit, first lane digit): the
 // source row (l0 +- 1, lane digit -+ 1) sits in the neighbouring lane, whose lead
@@ -417,8 +419,7 @@ __device__ __forceinline__ void hop_lane_pairs(const Lane<T, Q, L, LD> &ln, cons
 }
 
 template <typename T, int Q, int L, int LD, int C, int NRHS>
-__device__ __forceinline__ void hop_terms(const Lane<T, Q, L, LD> &ln, const T *base, const T *ownr, const T *owni,
-                                          T *Sr, T *Si) {
+__device__ __forceinline__ void hop_terms(const Lane<T, Q, L, LD> &ln, const T *base, T *Sr, T *Si) {
   using G = Geo<T, Q, L, LD>;
   constexpr bool RBL = C >= 0;
   constexpr int NO = RBL ? G::H : G::EPL;
@@ -503,7 +504,7 @@ __device__ __forceinline__ void apply_Hc(const Lane<T, Q, L, LD> &ln, const T *c
     }
   }
   lane_digit_terms<T, Q, L, LD, G::EPL>(ln, lor, loi, hir, hii, n, Sr, Si);
-  if constexpr (HOP) hop_terms<T, Q, L, LD, -1, 1>(ln, ln.xb, vr, vi, Sr, Si);   // reads the record above
+  if constexpr (HOP) hop_terms<T, Q, L, LD, -1, 1>(ln, ln.xb, Sr, Si);   // reads the record above
 }
 
 // Per-step control coefficients: c'_j for register digits, per-lane lowering
@@ -643,7 +644,7 @@ __device__ __forceinline__ void apply_half(const Lane<T, Q, L, LD> &ln, const Co
   lane_exchange<T, Q, L, LD, G::H, HOP ? G::H : 0>(ln, vr + IN, vi + IN, n, owr, owi);
   apply_half_regs<T, Q, L, LD, C>(ln, cf, vr, vi, Sr, Si);
   lane_digit_terms<T, Q, L, LD, G::H>(ln, cf.lor, cf.loi, cf.hir, cf.hii, n, Sr, Si);
-  if constexpr (HOP) hop_terms<T, Q, L, LD, C, 1>(ln, ln.xb + xtail<T, G::H>(), owr, owi, Sr, Si);
+  if constexpr (HOP) hop_terms<T, Q, L, LD, C, 1>(ln, ln.xb + xtail<T, G::H>(), Sr, Si);
 }
 
 __device__ __forceinline__ int kit_of(const DevSys &s) { return s.kit_fixed > 0 ? s.kit_fixed : *s.kit; }
@@ -815,7 +816,7 @@ __device__ __forceinline__ void half_sweep2(const Lane<T, Q, L, LD> &ln, const C
   apply_half_regs<T, Q, L, LD, C>(ln, cf, var, vai, Sr, Si);
   apply_half_regs<T, Q, L, LD, C>(ln, cf, vbr, vbi, Sr + G::H, Si + G::H);
   lane_digit_terms<T, Q, L, LD, 2 * G::H>(ln, cf.lor, cf.loi, cf.hir, cf.hii, n, Sr, Si);
-  if constexpr (HOP) hop_terms<T, Q, L, LD, C, 2>(ln, ln.xb + xtail<T, 2 * G::H>(), orr, ori, Sr, Si);
+  if constexpr (HOP) hop_terms<T, Q, L, LD, C, 2>(ln, ln.xb + xtail<T, 2 * G::H>(), Sr, Si);
 #pragma unroll
   for (int o = 0; o < G::H; ++o) {
     jacobi_update<T, Q, L, LD, REV>(ln, OUT + o, Sr[o], Si[o], xar[OUT + o], xai[OUT + o], war[OUT + o], wai[OUT + o]);
