@@ -188,6 +188,19 @@ __device__ __forceinline__ void xget(const T *buf, int lane, T *v) {
   }
 }
 
+// record of lane `src` (0..63) -> v[0..NV)
+template <typename T, int NV>
+__device__ __forceinline__ void xget_from(const T *buf, int src, T *v) {
+  using X = XRec<T, NV>;
+  const T *p = buf + (kGuard + src) * X::PE;
+#pragma unroll
+  for (int q = 0; q < X::NP; ++q) {
+    const T *sp = p + q * X::PSTRIDE;
+#pragma unroll
+    for (int i = 0; i < X::PE; ++i) v[q * X::PE + i] = sp[i];
+  }
+}
+
 // ---------------------------------------------------------------------------- per-lane state
 
 template <typename T, int Q, int L, int LD>
@@ -214,11 +227,13 @@ struct Lane {
   T hla[NPL], hlb[NPL];         // lane-digit pairs (R+jj, R+jj+1): full A and B weights
   T hsa, hsb;                   // pair (R-1, R): (dt/2) J_{R-1} sqrt(l_R), (dt/2) J_{R-1} sqrt(l_R + 1)
 
-  __device__ void init(const DevSys &s, int cg, T *xbuf) {
+  // half: the two halves of the wavefront hold the same columns (split backward sweep)
+  __device__ void init(const DevSys &s, int cg, T *xbuf, bool half = false) {
     xb = xbuf;
     lane = threadIdx.x;
-    const int slot = lane / G::LPCP;
-    sub = lane % G::LPCP;
+    const int hl = half ? (lane & 31) : lane;
+    const int slot = hl / G::LPCP;
+    sub = hl % G::LPCP;
     col = cg * G::CPW + slot;
     valid = (sub < G::LPC) && (col < s.E);
     par = 0;
@@ -1140,6 +1155,160 @@ struct SeriesBuf {
   static_assert(RB >= 1, "reduction buffer too small");
 };
 
+// Layouts whose columns fill at most half a wavefront (E * LPCP <= 32: the 2-level
+// 2- and 3-qubit systems, the 2-qubit 3- and 4-level ones) split the backward
+// sweep's two right-hand sides over the two halves: lanes 0..31 reconstruct the
+// state, lanes 32..63 propagate the adjoint of the same columns, with the same
+// instructions.  A lane then solves one system per step instead of two; these
+// windows are latency-bound serial chains, so the step gets shorter.
+template <typename G, int Q>
+constexpr bool split_rhs() { return (1 << Q) * G::LPCP <= 32; }
+
+template <typename T, int Q, int L, int LD, bool HOP>
+__device__ __forceinline__ void backward_item_split(const DevSys &s, int m, int cg, T *red, T *xb) {
+  using G = Geo<T, Q, L, LD>;
+  const int item = m * s.ncg + cg;
+  Lane<T, Q, L, LD> ln;
+  ln.init(s, cg, xb, true);
+  if constexpr (HOP) ln.init_hop(s);
+  const bool adj = ln.lane >= 32;                   // this lane's system: state (false) or adjoint (true)
+
+  double ar[G::EPL], ai[G::EPL];                    // U (state lanes) or Lambda (adjoint lanes), FP64
+  {
+    const double2 *uf = reinterpret_cast<const double2 *>(s.Ufin) + ((size_t)m * s.E + ln.col) * s.N;
+    const double E2 = (double)s.E * (double)s.E;
+    const double gr = s.scal[4] / E2, gi = s.scal[5] / E2;
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {
+      ar[e] = ai[e] = 0.0;
+      if (!ln.valid) continue;
+      const int r = ln.row(e);
+      const double2 u = uf[r];
+      if (!adj) {
+        ar[e] = u.x;
+        ai[e] = u.y;
+      } else if (m < s.M - 1) {   // mu/2 (W^m - U^m)
+        const double2 w = reinterpret_cast<const double2 *>(s.W)[((size_t)m * s.E + ln.col) * s.N + r];
+        ar[e] = 0.5 * s.mu * (w.x - u.x);
+        ai[e] = 0.5 * s.mu * (w.y - u.y);
+      } else {                    // gamma V / E^2 (the split terminal condition, see backward_item)
+        const double2 v = reinterpret_cast<const double2 *>(s.V)[(size_t)ln.col * s.N + r];
+        ar[e] = gr * v.x - gi * v.y;
+        ai[e] = gr * v.y + gi * v.x;
+      }
+    }
+  }
+  const long long k0 = s.kstart[m], k1 = s.kstart[m + 1];
+  const int kit = kit_of(s);
+  const T *ctrl = reinterpret_cast<const T *>(s.ctrl);
+  double *ser = s.series + (size_t)item * s.maxlen * 2 * Q;
+  int jr = 0, ic = 0;
+  if (s.ckpt_every > 0) {
+    jr = (int)(k1 - 1 - k0) % s.ckpt_every;
+    ic = (int)(k1 - 1 - k0) / s.ckpt_every;
+  }
+  typename C2<T>::type cnext[Q];
+  load_ctrl<T, Q>(ctrl, k1 - 1, cnext);
+  for (long long k = k1 - 1; k >= k0; --k) {
+    typename C2<T>::type ccur[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) ccur[j] = cnext[j];
+    load_ctrl<T, Q>(ctrl, k > k0 ? k - 1 : k, cnext);
+    Coef<T, Q, L, LD> cf;
+    step_coeffs<T, Q, L, LD>(ln, ccur, cf);
+    T ur[G::EPL], ui[G::EPL], wr[G::EPL], wi[G::EPL];
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {
+      ur[e] = (T)ar[e];
+      ui[e] = (T)ai[e];
+    }
+    solve_increment<T, Q, L, LD, true, HOP>(ln, kit, cf, ur, ui, wr, wi);
+    // own solution (z or y) and the other half's (lane ^ 32)
+    T vr[G::EPL], vi[G::EPL], pr[G::EPL], pi[G::EPL];
+    {
+      T rec[2 * G::EPL], oth[2 * G::EPL];
+#pragma unroll
+      for (int e = 0; e < G::EPL; ++e) {
+        vr[e] = ur[e] + wr[e];
+        vi[e] = ui[e] + wi[e];
+        rec[2 * e] = vr[e];
+        rec[2 * e + 1] = vi[e];
+      }
+      wave_sync();
+      xput<T, 2 * G::EPL>(ln.xb, ln.lane, rec);
+      wave_sync();
+      xget_from<T, 2 * G::EPL>(ln.xb, ln.lane ^ 32, oth);
+      wave_sync();
+#pragma unroll
+      for (int e = 0; e < G::EPL; ++e) {
+        pr[e] = oth[2 * e];
+        pi[e] = oth[2 * e + 1];
+      }
+    }
+    T zr[G::EPL], zi[G::EPL], yr[G::EPL], yi[G::EPL];
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {
+      zr[e] = adj ? pr[e] : vr[e];
+      zi[e] = adj ? pi[e] : vi[e];
+      yr[e] = adj ? vr[e] : pr[e];
+      yi[e] = adj ? vi[e] : pi[e];
+    }
+    // inner products (both halves compute them; the adjoint half contributes zeros)
+    T s1[Q], s2[Q];
+    inner_register_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
+    inner_lane_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
+    {
+      using SB = SeriesBuf<T, Q>;
+      const int idx = (int)(k - k0);
+      T *slot = red + (idx % SB::RB) * SB::RS + ln.lane;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        slot[(2 * j) * SB::VS] = adj ? (T)0 : s1[j];
+        slot[(2 * j + 1) * SB::VS] = adj ? (T)0 : s2[j];
+      }
+      if (idx % SB::RB == 0) {             // steps idx .. idx+RB-1 are buffered: flush
+        __syncthreads();
+        const int r = ln.lane / SB::NV, vv = ln.lane % SB::NV;
+        if (r < SB::RB && idx + r < (int)(k1 - k0)) {
+          const T *col = red + r * SB::RS + vv * SB::VS;
+          double acc = 0.0;
+#pragma unroll 8
+          for (int l = 0; l < 64; ++l) acc += (double)col[l];
+          ser[(size_t)(idx + r) * SB::NV + vv] = acc;
+        }
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {
+      ar[e] += 2.0 * (double)wr[e];
+      ai[e] += 2.0 * (double)wi[e];
+    }
+    if (s.ckpt_every > 0) {
+      if (jr == 0 && ic > 0 && !adj && ln.valid) {   // re-sync the state to the stored U_k
+        const double2 *cp =
+            reinterpret_cast<const double2 *>(s.ckpt) + (((size_t)m * s.ncp + (ic - 1)) * s.E + ln.col) * s.N;
+#pragma unroll
+        for (int e = 0; e < G::EPL; ++e) {
+          const double2 c = cp[ln.row(e)];
+          ar[e] = c.x;
+          ai[e] = c.y;
+        }
+      }
+      if (jr == 0) {
+        jr = s.ckpt_every - 1;
+        --ic;
+      } else {
+        --jr;
+      }
+    }
+  }
+  if (!ln.valid || !adj) return;
+  double2 *l0 = reinterpret_cast<double2 *>(s.lam0) + ((size_t)m * s.E + ln.col) * s.N;
+#pragma unroll
+  for (int e = 0; e < G::EPL; ++e) l0[ln.row(e)] = double2{ar[e], ai[e]};
+}
+
 // One wavefront per (window, column group).  Starting from U^m(t_m) and the
 // terminal condition of eq. terminal, each step k (descending) solves
 //   (I - i dt/2 H_k) [z, y] = [U_{k+1}, Lambda_{k+1}]
@@ -1157,6 +1326,10 @@ struct SeriesBuf {
 template <typename T, int Q, int L, int LD, bool HOP>
 __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T *red, T *xb) {
   using G = Geo<T, Q, L, LD>;
+  if constexpr (split_rhs<G, Q>()) {
+    backward_item_split<T, Q, L, LD, HOP>(s, m, cg, red, xb);
+    return;
+  }
   const int item = m * s.ncg + cg;
   Lane<T, Q, L, LD> ln;
   ln.init(s, cg, xb);
