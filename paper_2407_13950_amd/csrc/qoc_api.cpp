@@ -247,6 +247,9 @@ int qoc_create(const qoc_system_desc *desc, qoc_ctx **out) {
     }
   }
   s.fp64 = fp64; s.ld = ld; s.cpw = cpw; s.ncg = (E + cpw - 1) / cpw; s.maxlen = maxlen;
+  // layouts with at least two columns per wavefront split the backward sweep's state and
+  // adjoint over the two halves of a wavefront: cpw/2 columns per backward wavefront
+  s.ncg_b = cpw >= 2 ? (E + cpw / 2 - 1) / (cpw / 2) : s.ncg;
   s.ckpt_every = (D.checkpoint_every > 0 && D.checkpoint_every < maxlen) ? D.checkpoint_every : 0;
   s.ncp = s.ckpt_every ? (int)((maxlen - 1) / s.ckpt_every) : 0;
   s.kit_fixed = D.fixed_point_iters;
@@ -273,7 +276,7 @@ int qoc_create(const qoc_system_desc *desc, qoc_ctx **out) {
   ALLOC(s.ckpt, sizeof(double) * 2 * nst * s.ncp);
   ALLOC(s.partials, sizeof(double) * 4 * M);
   ALLOC(s.scal, sizeof(double) * (5 + M));
-  ALLOC(s.series, sizeof(double) * (size_t)M * s.ncg * maxlen * 2 * q);
+  ALLOC(s.series, sizeof(double) * (size_t)M * s.ncg_b * maxlen * 2 * q);
   ALLOC(s.xy, sizeof(double) * (size_t)NT * 2 * q);
   ALLOC(s.grad_alpha, sizeof(double) * c->d);
   ALLOC(s.grad_W, sizeof(double) * 2 * (size_t)(M - 1) * E * N);
@@ -579,10 +582,10 @@ int qoc_batch_run(qoc_batch *b, qoc_ctx *const *ctxs, int32_t n, const int32_t *
       long long len = 0;
       // window length from the floor split
       len = (long long)(((__int128)(m + 1) * c->NT) / c->M) - (long long)(((__int128)m * c->NT) / c->M);
-      for (int cg = 0; cg < c->dev.ncg; ++cg) {
-        const int4 v = make_int4(i, m, cg, c->shape);
-        fwd.push_back({len * per_lane * c->q, v});
-        if (g) bwd.push_back({2 * len * per_lane * c->q, v});
+      for (int cg = 0; cg < c->dev.ncg; ++cg) fwd.push_back({len * per_lane * c->q, make_int4(i, m, cg, c->shape)});
+      if (g) {
+        const long long bcost = (c->dev.cpw >= 2 ? 1 : 2) * len * per_lane * c->q;   // split: one system per lane
+        for (int cg = 0; cg < c->dev.ncg_b; ++cg) bwd.push_back({bcost, make_int4(i, m, cg, c->shape)});
       }
     }
     for (int k = 0; k < qoc::SK_COUNT; ++k) {

@@ -22,7 +22,9 @@ struct DevSys {
   int fp64;                 // 1: propagation in double, 0: float
   int ld;                   // lane digits of the register layout
   int cpw;                  // state columns per wavefront
-  int ncg;                  // column groups (wavefronts) per window
+  int ncg;                  // column groups (wavefronts) per window, forward sweep
+  int ncg_b;                // column groups per window of the backward sweep (twice as many where it
+                            // splits state and adjoint over the halves of a wavefront)
   long long maxlen;         // longest window, steps
   int ckpt_every;           // checkpoint spacing in steps (0 = none)
   int ncp;                  // checkpoints stored per window

@@ -227,14 +227,14 @@ struct Lane {
   T hla[NPL], hlb[NPL];         // lane-digit pairs (R+jj, R+jj+1): full A and B weights
   T hsa, hsb;                   // pair (R-1, R): (dt/2) J_{R-1} sqrt(l_R), (dt/2) J_{R-1} sqrt(l_R + 1)
 
-  // half: the two halves of the wavefront hold the same columns (split backward sweep)
+  // half: the two halves of the wavefront hold the same CPW/2 columns (split backward sweep)
   __device__ void init(const DevSys &s, int cg, T *xbuf, bool half = false) {
     xb = xbuf;
     lane = threadIdx.x;
     const int hl = half ? (lane & 31) : lane;
     const int slot = hl / G::LPCP;
     sub = hl % G::LPCP;
-    col = cg * G::CPW + slot;
+    col = cg * (half ? G::CPW / 2 : G::CPW) + slot;
     valid = (sub < G::LPC) && (col < s.E);
     par = 0;
 #pragma unroll
@@ -1155,19 +1155,20 @@ struct SeriesBuf {
   static_assert(RB >= 1, "reduction buffer too small");
 };
 
-// Layouts whose columns fill at most half a wavefront (E * LPCP <= 32: the 2-level
-// 2- and 3-qubit systems, the 2-qubit 3- and 4-level ones) split the backward
-// sweep's two right-hand sides over the two halves: lanes 0..31 reconstruct the
-// state, lanes 32..63 propagate the adjoint of the same columns, with the same
-// instructions.  A lane then solves one system per step instead of two; these
-// windows are latency-bound serial chains, so the step gets shorter.
+// Layouts with two or more columns per wavefront (a column spans at most 32 lanes)
+// split the backward sweep's two right-hand sides over the two halves of a
+// wavefront: lanes 0..31 reconstruct the state and lanes 32..63 propagate the
+// adjoint of the same CPW/2 columns, with the same instructions (DevSys.ncg_b
+// backward wavefronts per window).  A lane then solves one system per step instead
+// of two: these windows are latency-bound serial chains (few wavefronts), and the
+// step gets shorter.
 template <typename G, int Q>
-constexpr bool split_rhs() { return (1 << Q) * G::LPCP <= 32; }
+constexpr bool split_rhs() { return G::CPW >= 2; }
 
 template <typename T, int Q, int L, int LD, bool HOP>
 __device__ __forceinline__ void backward_item_split(const DevSys &s, int m, int cg, T *red, T *xb) {
   using G = Geo<T, Q, L, LD>;
-  const int item = m * s.ncg + cg;
+  const int item = m * s.ncg_b + cg;
   Lane<T, Q, L, LD> ln;
   ln.init(s, cg, xb, true);
   if constexpr (HOP) ln.init_hop(s);
@@ -1330,7 +1331,7 @@ __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T 
     backward_item_split<T, Q, L, LD, HOP>(s, m, cg, red, xb);
     return;
   }
-  const int item = m * s.ncg + cg;
+  const int item = m * s.ncg_b + cg;
   Lane<T, Q, L, LD> ln;
   ln.init(s, cg, xb);
   if constexpr (HOP) ln.init_hop(s);
@@ -1471,7 +1472,7 @@ void k_backward(DevSys s, int nitems) {
   __shared__ T red[red_elems<T>()];
   __shared__ __align__(16) T xb[xchg_bytes<T, HOP>() / sizeof(T)];
   xchg_clear<T, HOP>(xb);
-  backward_item<T, Q, L, LD, HOP>(s, item / s.ncg, item % s.ncg, red, xb);
+  backward_item<T, Q, L, LD, HOP>(s, item / s.ncg_b, item % s.ncg_b, red, xb);
 }
 
 // ---------------------------------------------------------------------------- small FP64 kernels
@@ -1639,8 +1640,8 @@ __device__ void series_reduce_block(const DevSys &s, int blk) {
   double acc[12];
 #pragma unroll
   for (int i = 0; i < 12; ++i) acc[i] = 0.0;
-  for (int cg = 0; cg < s.ncg; ++cg) {       // one contiguous record of 2q values per column group
-    const double *src = s.series + (((size_t)m * s.ncg + cg) * s.maxlen + kk) * w;
+  for (int cg = 0; cg < s.ncg_b; ++cg) {     // one contiguous record of 2q values per column group
+    const double *src = s.series + (((size_t)m * s.ncg_b + cg) * s.maxlen + kk) * w;
 #pragma unroll
     for (int i = 0; i < 12; ++i)
       if (i < w) acc[i] += src[i];
@@ -1829,7 +1830,7 @@ int phase_T(const DevSys &s, int phase, hipStream_t st, double *Wout, double *Uf
       small<T, SK_BFINAL>(s, st);
       break;
     case PHASE_BACKWARD:
-      hipLaunchKernelGGL(K.bwd, dim3(grid8(nitems)), dim3(64), 0, st, s, nitems);
+      hipLaunchKernelGGL(K.bwd, dim3(grid8(s.M * s.ncg_b)), dim3(64), 0, st, s, s.M * s.ncg_b);
       break;
     case PHASE_PROJECT:
       small<T, SK_SERIES>(s, st);
