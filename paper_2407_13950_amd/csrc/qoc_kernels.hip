@@ -1371,17 +1371,9 @@ __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T 
     ic = (int)(k1 - 1 - k0) / s.ckpt_every;
   }
 
-  typename C2<T>::type cnext[Q];
-  if constexpr (ctrl_ahead<G>()) load_ctrl<T, Q>(ctrl, k1 - 1, cnext);
-  for (long long k = k1 - 1; k >= k0; --k) {
+  for (long long k = k1 - 1; k >= k0; --k) {      // (one column per wavefront: the controls are not loaded ahead)
     typename C2<T>::type ccur[Q];
-    if constexpr (ctrl_ahead<G>()) {
-#pragma unroll
-      for (int j = 0; j < Q; ++j) ccur[j] = cnext[j];
-      load_ctrl<T, Q>(ctrl, k > k0 ? k - 1 : k, cnext);
-    } else {
-      load_ctrl<T, Q>(ctrl, k, ccur);
-    }
+    load_ctrl<T, Q>(ctrl, k, ccur);
     Coef<T, Q, L, LD> cf;
     step_coeffs<T, Q, L, LD>(ln, ccur, cf);
     T ur[G::EPL], ui[G::EPL], lr[G::EPL], li[G::EPL];
