@@ -521,8 +521,13 @@ struct qoc_batch {
   size_t stage_bytes = 0;
   hipEvent_t uploaded = nullptr; // staging may be rewritten once this has passed
   bool pending = false;
+  hipStream_t aux = nullptr;      // backward items of two wavefronts run here (default priority)
+  hipEvent_t fork = nullptr, join = nullptr;
   ~qoc_batch() {
     if (uploaded) { (void)hipEventSynchronize(uploaded); (void)hipEventDestroy(uploaded); }
+    if (aux) { (void)hipStreamSynchronize(aux); (void)hipStreamDestroy(aux); }
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
     (void)hipFree(d_sys); (void)hipFree(d_items); (void)hipFree(d_blocks);
     (void)hipHostFree(h_stage);
   }
@@ -543,6 +548,9 @@ int qoc_batch_create(int32_t device, int32_t max_contexts, int64_t max_items, qo
   if (e == hipSuccess) e = hipMalloc(&b->d_blocks, sizeof(int2) * b->max_blocks);
   if (e == hipSuccess) e = hipHostMalloc(&b->h_stage, b->stage_bytes, hipHostMallocDefault);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join, hipEventDisableTiming);
   if (e != hipSuccess) { delete b; return fail(QOC_ENOMEM, std::string("qoc_batch_create: ") + hipGetErrorString(e)); }
   *out = b;
   return QOC_OK;
@@ -572,7 +580,7 @@ int qoc_batch_run(qoc_batch *b, qoc_ctx *const *ctxs, int32_t n, const int32_t *
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   // propagation items, longest first (cost ~ steps x entries per lane x qubits)
   struct It { long long cost; int4 v; };
-  std::vector<It> fwd, bwd;
+  std::vector<It> fwd, bwd, xw;
   long long nblocks = 0;
   for (int i = 0; i < n; ++i) {
     const qoc_ctx *c = ctxs[i];
@@ -584,8 +592,9 @@ int qoc_batch_run(qoc_batch *b, qoc_ctx *const *ctxs, int32_t n, const int32_t *
       len = (long long)(((__int128)(m + 1) * c->NT) / c->M) - (long long)(((__int128)m * c->NT) / c->M);
       for (int cg = 0; cg < c->dev.ncg; ++cg) fwd.push_back({len * per_lane * c->q, make_int4(i, m, cg, c->shape)});
       if (g) {
-        const long long bcost = (c->dev.cpw >= 2 ? 1 : 2) * len * per_lane * c->q;   // split: one system per lane
-        for (int cg = 0; cg < c->dev.ncg_b; ++cg) bwd.push_back({bcost, make_int4(i, m, cg, c->shape)});
+        const bool two = qoc::xw_backward(c->dev);                                      // two wavefronts per item
+        const long long bcost = (c->dev.cpw >= 2 || two ? 1 : 2) * len * per_lane * c->q;   // one system per lane
+        for (int cg = 0; cg < c->dev.ncg_b; ++cg) (two ? xw : bwd).push_back({bcost, make_int4(i, m, cg, c->shape)});
       }
     }
     for (int k = 0; k < qoc::SK_COUNT; ++k) {
@@ -593,12 +602,13 @@ int qoc_batch_run(qoc_batch *b, qoc_ctx *const *ctxs, int32_t n, const int32_t *
       if (!gk || g) nblocks += qoc::small_blocks(c->dev, k);
     }
   }
-  if ((long long)fwd.size() > b->max_items || (long long)bwd.size() > b->max_items)
+  if ((long long)fwd.size() > b->max_items || (long long)(bwd.size() + xw.size()) > b->max_items)
     return fail(QOC_EINVAL, "qoc_batch_run: more propagation items than the batch was created for");
   if (nblocks > b->max_blocks) return fail(QOC_EINVAL, "qoc_batch_run: small-kernel table exceeds the batch capacity");
   auto by_cost = [](const It &x, const It &y) { return x.cost > y.cost; };
   std::stable_sort(fwd.begin(), fwd.end(), by_cost);
   std::stable_sort(bwd.begin(), bwd.end(), by_cost);
+  std::stable_sort(xw.begin(), xw.end(), by_cost);
 
   // the previous run's uploads must have left the staging buffer
   if (b->pending) HIP_OR_RETURN(hipEventSynchronize(b->uploaded));
@@ -609,13 +619,19 @@ int qoc_batch_run(qoc_batch *b, qoc_ctx *const *ctxs, int32_t n, const int32_t *
   for (int i = 0; i < n; ++i) hs[i] = ctxs[i]->dev;
   for (size_t k = 0; k < fwd.size(); ++k) hi[k] = fwd[k].v;
   for (size_t k = 0; k < bwd.size(); ++k) hi[fwd.size() + k] = bwd[k].v;
+  for (size_t k = 0; k < xw.size(); ++k) hi[fwd.size() + bwd.size() + k] = xw[k].v;
   qoc::BatchPlan plan{};
   plan.fp64 = fp64;
   plan.sys = b->d_sys;
   plan.fwd_items = b->d_items;
   plan.bwd_items = b->d_items + fwd.size();
+  plan.xw_items = b->d_items + fwd.size() + bwd.size();
   plan.n_fwd = (int)fwd.size();
   plan.n_bwd = (int)bwd.size();
+  plan.n_xw = (int)xw.size();
+  plan.aux = b->aux;
+  plan.fork = b->fork;
+  plan.join = b->join;
   long long off = 0;
   for (int k = 0; k < qoc::SK_COUNT; ++k) {
     const bool gk = k == qoc::SK_SERIES || k == qoc::SK_PROJECT || k == qoc::SK_GRADW;
@@ -630,7 +646,8 @@ int qoc_batch_run(qoc_batch *b, qoc_ctx *const *ctxs, int32_t n, const int32_t *
     off += cnt;
   }
   HIP_OR_RETURN(hipMemcpyAsync(b->d_sys, hs, sizeof(qoc::DevSys) * n, hipMemcpyHostToDevice, st));
-  HIP_OR_RETURN(hipMemcpyAsync(b->d_items, hi, sizeof(int4) * (fwd.size() + bwd.size()), hipMemcpyHostToDevice, st));
+  HIP_OR_RETURN(hipMemcpyAsync(b->d_items, hi, sizeof(int4) * (fwd.size() + bwd.size() + xw.size()),
+                               hipMemcpyHostToDevice, st));
   HIP_OR_RETURN(hipMemcpyAsync(b->d_blocks, hb, sizeof(int2) * std::max<long long>(off, 1), hipMemcpyHostToDevice, st));
   HIP_OR_RETURN(hipEventRecord(b->uploaded, st));
   b->pending = true;

@@ -77,11 +77,20 @@ int launch_phase(const DevSys &s, int phase, hipStream_t st, double *Wout = null
 // Several systems evaluated together: the propagation phases run as one launch
 // over all (system, window, column group) items, each small kernel as one launch
 // over a (system, block) table.  All systems share the precision `fp64`.
+// The backward sweep of a one-column-per-wavefront layout runs as two wavefronts per
+// (window, column group), state and adjoint, when the launch has at most one
+// wavefront per SIMD otherwise (1024 SIMDs).  A function of the system alone, so a
+// batched evaluation makes the same choice as a solo one.
+inline bool xw_backward(const DevSys &s) { return s.cpw == 1 && (long long)s.M * s.ncg_b <= 1024; }
+
 struct BatchPlan {
   const DevSys *sys;              // [n] device copy of the systems
   const int4 *fwd_items;          // [n_fwd] (system, window, column group, shape), longest first
   const int4 *bwd_items;          // [n_bwd]
-  int n_fwd, n_bwd;
+  const int4 *xw_items;           // [n_xw] backward items of xw_backward systems (two wavefronts each)
+  int n_fwd, n_bwd, n_xw;
+  hipStream_t aux;                // the xw items run here, forked from and joined to the caller's stream
+  hipEvent_t fork, join;
   const int2 *blocks[SK_COUNT];   // per small kernel: (system, block within the system)
   int n_blocks[SK_COUNT];
   int fp64;

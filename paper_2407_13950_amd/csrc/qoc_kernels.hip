@@ -131,7 +131,7 @@ __device__ __forceinline__ void wave_sync() {
 template <typename T, bool HOP>
 __device__ __forceinline__ void xchg_clear(T *buf) {
   float4 *p = reinterpret_cast<float4 *>(buf);
-  for (int i = threadIdx.x; i < xchg_bytes<T, HOP>() / 16; i += 64) p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int i = threadIdx.x & 63; i < xchg_bytes<T, HOP>() / 16; i += 64) p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
   wave_sync();
 }
 
@@ -230,7 +230,7 @@ struct Lane {
   // half: the two halves of the wavefront hold the same CPW/2 columns (split backward sweep)
   __device__ void init(const DevSys &s, int cg, T *xbuf, bool half = false) {
     xb = xbuf;
-    lane = threadIdx.x;
+    lane = threadIdx.x & 63;                        // lane within this wavefront
     const int hl = half ? (lane & 31) : lane;
     const int slot = hl / G::LPCP;
     sub = hl % G::LPCP;
@@ -1467,6 +1467,162 @@ void k_backward(DevSys s, int nitems) {
   backward_item<T, Q, L, LD, HOP>(s, item / s.ncg_b, item % s.ncg_b, red, xb);
 }
 
+// Two wavefronts per (window, column group) for the one-column-per-wavefront layout
+// when a launch has few wavefronts (at most one per SIMD): wavefront 0 reconstructs
+// the state and wavefront 1 propagates the adjoint, with the same instructions, so
+// each solves one system per step.  Every step wavefront 0 passes z to wavefront 1
+// through a double-buffered LDS record (one block barrier per step, taken by both
+// wavefronts on every iteration), and wavefront 1 takes the inner products.
+template <typename T, int Q, int L, int LD, bool HOP>
+__device__ __forceinline__ void backward_item_xw(const DevSys &s, int m, int cg, T *red, T *xb, T *zb) {
+  using G = Geo<T, Q, L, LD>;
+  const int wv = threadIdx.x >> 6;                  // 0: state, 1: adjoint (uniform per wavefront)
+  const int item = m * s.ncg_b + cg;
+  Lane<T, Q, L, LD> ln;
+  ln.init(s, cg, xb);
+  if constexpr (HOP) ln.init_hop(s);
+
+  double ar[G::EPL], ai[G::EPL];                    // U (wavefront 0) or Lambda (wavefront 1), FP64
+  {
+    const double2 *uf = reinterpret_cast<const double2 *>(s.Ufin) + ((size_t)m * s.E + ln.col) * s.N;
+    const double E2 = (double)s.E * (double)s.E;
+    const double gr = s.scal[4] / E2, gi = s.scal[5] / E2;
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {
+      ar[e] = ai[e] = 0.0;
+      if (!ln.valid) continue;
+      const int r = ln.row(e);
+      const double2 u = uf[r];
+      if (wv == 0) {
+        ar[e] = u.x;
+        ai[e] = u.y;
+      } else if (m < s.M - 1) {   // mu/2 (W^m - U^m)
+        const double2 w = reinterpret_cast<const double2 *>(s.W)[((size_t)m * s.E + ln.col) * s.N + r];
+        ar[e] = 0.5 * s.mu * (w.x - u.x);
+        ai[e] = 0.5 * s.mu * (w.y - u.y);
+      } else {                    // gamma V / E^2 (the split terminal condition, see backward_item)
+        const double2 v = reinterpret_cast<const double2 *>(s.V)[(size_t)ln.col * s.N + r];
+        ar[e] = gr * v.x - gi * v.y;
+        ai[e] = gr * v.y + gi * v.x;
+      }
+    }
+  }
+  const long long k0 = s.kstart[m], k1 = s.kstart[m + 1];
+  const int kit = kit_of(s);
+  const T *ctrl = reinterpret_cast<const T *>(s.ctrl);
+  double *ser = s.series + (size_t)item * s.maxlen * 2 * Q;
+  int jr = 0, ic = 0;
+  if (s.ckpt_every > 0) {
+    jr = (int)(k1 - 1 - k0) % s.ckpt_every;
+    ic = (int)(k1 - 1 - k0) / s.ckpt_every;
+  }
+  for (long long k = k1 - 1; k >= k0; --k) {
+    typename C2<T>::type ccur[Q];
+    load_ctrl<T, Q>(ctrl, k, ccur);
+    Coef<T, Q, L, LD> cf;
+    step_coeffs<T, Q, L, LD>(ln, ccur, cf);
+    T ur[G::EPL], ui[G::EPL], wr[G::EPL], wi[G::EPL];
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {
+      ur[e] = (T)ar[e];
+      ui[e] = (T)ai[e];
+    }
+    solve_increment<T, Q, L, LD, true, HOP>(ln, kit, cf, ur, ui, wr, wi);
+    T *zrec = zb + (size_t)(k & 1) * 64 * 2 * G::EPL + (size_t)ln.lane * 2 * G::EPL;
+    if (wv == 0) {
+#pragma unroll
+      for (int e = 0; e < G::EPL; ++e) {
+        zrec[2 * e] = ur[e] + wr[e];
+        zrec[2 * e + 1] = ui[e] + wi[e];
+      }
+    }
+    __syncthreads();                                // both wavefronts, every step
+    if (wv == 1) {
+      T zr[G::EPL], zi[G::EPL], yr[G::EPL], yi[G::EPL];
+#pragma unroll
+      for (int e = 0; e < G::EPL; ++e) {
+        zr[e] = zrec[2 * e];
+        zi[e] = zrec[2 * e + 1];
+        yr[e] = ur[e] + wr[e];
+        yi[e] = ui[e] + wi[e];
+      }
+      T s1[Q], s2[Q];
+      inner_register_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
+      inner_lane_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
+      using SB = SeriesBuf<T, Q>;
+      const int idx = (int)(k - k0);
+      T *slot = red + (idx % SB::RB) * SB::RS + ln.lane;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        slot[(2 * j) * SB::VS] = s1[j];
+        slot[(2 * j + 1) * SB::VS] = s2[j];
+      }
+      if (idx % SB::RB == 0) {             // steps idx .. idx+RB-1 are buffered: flush (this wavefront only)
+        wave_sync();
+        const int r = ln.lane / SB::NV, vv = ln.lane % SB::NV;
+        if (r < SB::RB && idx + r < (int)(k1 - k0)) {
+          const T *col = red + r * SB::RS + vv * SB::VS;
+          double acc = 0.0;
+#pragma unroll 8
+          for (int l = 0; l < 64; ++l) acc += (double)col[l];
+          ser[(size_t)(idx + r) * SB::NV + vv] = acc;
+        }
+        wave_sync();
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {
+      ar[e] += 2.0 * (double)wr[e];
+      ai[e] += 2.0 * (double)wi[e];
+    }
+    if (s.ckpt_every > 0) {
+      if (jr == 0 && ic > 0 && wv == 0 && ln.valid) {   // re-sync the state to the stored U_k
+        const double2 *cp =
+            reinterpret_cast<const double2 *>(s.ckpt) + (((size_t)m * s.ncp + (ic - 1)) * s.E + ln.col) * s.N;
+#pragma unroll
+        for (int e = 0; e < G::EPL; ++e) {
+          const double2 c = cp[ln.row(e)];
+          ar[e] = c.x;
+          ai[e] = c.y;
+        }
+      }
+      if (jr == 0) {
+        jr = s.ckpt_every - 1;
+        --ic;
+      } else {
+        --jr;
+      }
+    }
+  }
+  if (wv == 0 || !ln.valid) return;
+  double2 *l0 = reinterpret_cast<double2 *>(s.lam0) + ((size_t)m * s.E + ln.col) * s.N;
+#pragma unroll
+  for (int e = 0; e < G::EPL; ++e) l0[ln.row(e)] = double2{ar[e], ai[e]};
+}
+
+// Per block: wavefront 0's and wavefront 1's exchange buffers, the double-buffered z
+// record, and wavefront 1's series buffer.
+template <typename T, bool HOP>
+constexpr int xw_lds_elems() { return 2 * (xchg_bytes<T, HOP>() / (int)sizeof(T)) + 2 * 64 * 8 + red_elems<T>(); }
+
+template <typename T, int Q, int L, int LD, bool HOP>
+__global__ __launch_bounds__(128) void k_backward_xw(DevSys s, int nitems) {
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  if (item >= nitems) return;                       // uniform over the block
+  __shared__ __align__(16) T lds[xw_lds_elems<T, HOP>()];
+  constexpr int XE = xchg_bytes<T, HOP>() / (int)sizeof(T);
+  T *xb = lds + (threadIdx.x >> 6) * XE;
+  T *zb = lds + 2 * XE;
+  T *red = zb + 2 * 64 * 8;
+  xchg_clear<T, HOP>(xb);
+  backward_item_xw<T, Q, L, LD, HOP>(s, item / s.ncg_b, item % s.ncg_b, red, xb, zb);
+}
+
+template <typename T, int Q, int L, int LD, bool HOP>
+__device__ __forceinline__ void xw_item(const DevSys &s, int m, int cg, T *red, T *xb, T *zb) {
+  if constexpr (Geo<T, Q, L, LD>::CPW == 1) backward_item_xw<T, Q, L, LD, HOP>(s, m, cg, red, xb, zb);
+}
+
 // ---------------------------------------------------------------------------- small FP64 kernels
 
 // Fixed-point iteration count.  The Jacobi map w -> (D^{-1} - 1)u - i D^{-1} (dt/2) H_c (u + w)
@@ -1719,11 +1875,15 @@ struct Kernels {
   void (*fwd)(DevSys, double *, double *, int);
   void (*roll)(DevSys, double *, double *, int);
   void (*bwd)(DevSys, int);
+  void (*bwd_xw)(DevSys, int);     // two wavefronts per item (one-column layouts only)
 };
 
 template <typename T, int Q, int L, int LD, bool HOP>
 Kernels make() {
-  return Kernels{k_forward<T, Q, L, LD, false, HOP>, k_forward<T, Q, L, LD, true, HOP>, k_backward<T, Q, L, LD, HOP>};
+  void (*xw)(DevSys, int) = nullptr;
+  if constexpr (Geo<T, Q, L, LD>::CPW == 1) xw = k_backward_xw<T, Q, L, LD, HOP>;
+  return Kernels{k_forward<T, Q, L, LD, false, HOP>, k_forward<T, Q, L, LD, true, HOP>, k_backward<T, Q, L, LD, HOP>,
+                 xw};
 }
 
 // (q, L) -> lane digits, chosen so that each lane holds at most four entries
@@ -1795,6 +1955,26 @@ __global__ __launch_bounds__(64) void k_backward_batch(const DevSys *sys, const 
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(128) void k_backward_xw_batch(const DevSys *sys, const int4 *items) {
+  __shared__ __align__(16) T lds[xw_lds_elems<T, true>()];   // either variant
+  constexpr int XE = xchg_bytes<T, true>() / (int)sizeof(T);
+  T *xb = lds + (threadIdx.x >> 6) * XE;
+  T *zb = lds + 2 * XE;
+  T *red = zb + 2 * 64 * 8;
+  xchg_clear<T, true>(xb);
+  const int4 it = items[blockIdx.x];
+  const DevSys s = sys[it.x];
+  switch (it.w) {
+#define X(Q_, L_, LD_)                                                                         \
+    case SHAPE_##Q_##_##L_: xw_item<T, Q_, L_, LD_, false>(s, it.y, it.z, red, xb, zb); break; \
+    case N_SHAPES + SHAPE_##Q_##_##L_: xw_item<T, Q_, L_, LD_, true>(s, it.y, it.z, red, xb, zb); break;
+    QOC_SHAPES(X)
+#undef X
+    default: break;
+  }
+}
+
 int grid8(int n) { return (n + 7) / 8 * 8; }
 
 template <typename T, int K>
@@ -1822,7 +2002,10 @@ int phase_T(const DevSys &s, int phase, hipStream_t st, double *Wout, double *Uf
       small<T, SK_BFINAL>(s, st);
       break;
     case PHASE_BACKWARD:
-      hipLaunchKernelGGL(K.bwd, dim3(grid8(s.M * s.ncg_b)), dim3(64), 0, st, s, s.M * s.ncg_b);
+      if (xw_backward(s) && K.bwd_xw)
+        hipLaunchKernelGGL(K.bwd_xw, dim3(grid8(s.M * s.ncg_b)), dim3(128), 0, st, s, s.M * s.ncg_b);
+      else
+        hipLaunchKernelGGL(K.bwd, dim3(grid8(s.M * s.ncg_b)), dim3(64), 0, st, s, s.M * s.ncg_b);
       break;
     case PHASE_PROJECT:
       small<T, SK_SERIES>(s, st);
@@ -1861,7 +2044,18 @@ int batch_phase_T(const BatchPlan &p, int phase, hipStream_t st) {
       small_batched<T, SK_BFINAL>(p, st);
       break;
     case PHASE_BACKWARD:
+      if (p.n_xw > 0) {                   // the two-wavefront items run beside the others
+        hipError_t e = hipEventRecord(p.fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(p.aux, p.fork, 0);
+        if (e != hipSuccess) return (int)e;
+        hipLaunchKernelGGL(k_backward_xw_batch<T>, dim3(p.n_xw), dim3(128), 0, p.aux, p.sys, p.xw_items);
+      }
       if (p.n_bwd > 0) hipLaunchKernelGGL(k_backward_batch<T>, dim3(p.n_bwd), dim3(64), 0, st, p.sys, p.bwd_items);
+      if (p.n_xw > 0) {
+        hipError_t e = hipEventRecord(p.join, p.aux);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, p.join, 0);
+        if (e != hipSuccess) return (int)e;
+      }
       break;
     case PHASE_PROJECT:
       small_batched<T, SK_SERIES>(p, st);
