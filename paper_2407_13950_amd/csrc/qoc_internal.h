@@ -81,7 +81,10 @@ int launch_phase(const DevSys &s, int phase, hipStream_t st, double *Wout = null
 // (window, column group), state and adjoint, when the launch has at most one
 // wavefront per SIMD otherwise (1024 SIMDs).  A function of the system alone, so a
 // batched evaluation makes the same choice as a solo one.
-inline bool xw_backward(const DevSys &s) { return s.cpw == 1 && (long long)s.M * s.ncg_b <= 1024; }
+#ifndef QOC_XW_MAX_ITEMS
+#define QOC_XW_MAX_ITEMS 1024
+#endif
+inline bool xw_backward(const DevSys &s) { return s.cpw == 1 && (long long)s.M * s.ncg_b <= QOC_XW_MAX_ITEMS; }
 
 struct BatchPlan {
   const DevSys *sys;              // [n] device copy of the systems
