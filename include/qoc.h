@@ -176,7 +176,11 @@ int qoc_rollout(qoc_ctx *ctx, double *W_out, double *U_out, int32_t where);
  * QOC_EINVAL (mixed precision/device, duplicates, more contexts or items than
  * the batch was created for), QOC_ESTATE (a context without controls/states).
  * Results agree with the single-context calls bit for bit (same kernels, same
- * reduction order). */
+ * reduction order).  The backward sweeps of 4-qubit 4-level contexts with at most
+ * 64 windows (two wavefronts per item) run on a stream the batch owns, forked from
+ * hip_stream and joined back to it within the call's work, so the caller sees
+ * ordinary stream order.  max_items bounds the forward items and, separately, the
+ * backward items (window x backward column group) of one call. */
 typedef struct qoc_batch qoc_batch;
 int qoc_batch_create(int32_t device, int32_t max_contexts, int64_t max_items, qoc_batch **out);
 int qoc_batch_destroy(qoc_batch *b);
