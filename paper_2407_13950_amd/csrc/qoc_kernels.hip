@@ -1155,6 +1155,103 @@ struct SeriesBuf {
   static_assert(RB >= 1, "reduction buffer too small");
 };
 
+// ---- pieces shared by the backward sweep variants
+
+// Start values of window m for one lane: U^m(t_m) (state) or the terminal adjoint of
+// eq. terminal, mu/2 (W^m - U^m), or gamma V/E^2 for the last window (the split
+// form: the part -U^M/E obeys the state's recursion, adds nothing to the control
+// gradient, and returns in the W-gradient; App. B, eq. back-prop-2).
+template <typename T, int Q, int L, int LD>
+__device__ __forceinline__ void backward_start(const DevSys &s, int m, const Lane<T, Q, L, LD> &ln, bool adjoint,
+                                               double *ar, double *ai) {
+  using G = Geo<T, Q, L, LD>;
+  const double2 *uf = reinterpret_cast<const double2 *>(s.Ufin) + ((size_t)m * s.E + ln.col) * s.N;
+  const double E2 = (double)s.E * (double)s.E;
+  const double gr = s.scal[4] / E2, gi = s.scal[5] / E2;
+#pragma unroll
+  for (int e = 0; e < G::EPL; ++e) {
+    ar[e] = ai[e] = 0.0;
+    if (!ln.valid) continue;
+    const int r = ln.row(e);
+    const double2 u = uf[r];
+    if (!adjoint) {
+      ar[e] = u.x;
+      ai[e] = u.y;
+    } else if (m < s.M - 1) {
+      const double2 w = reinterpret_cast<const double2 *>(s.W)[((size_t)m * s.E + ln.col) * s.N + r];
+      ar[e] = 0.5 * s.mu * (w.x - u.x);
+      ai[e] = 0.5 * s.mu * (w.y - u.y);
+    } else {
+      const double2 v = reinterpret_cast<const double2 *>(s.V)[(size_t)ln.col * s.N + r];
+      ar[e] = gr * v.x - gi * v.y;
+      ai[e] = gr * v.y + gi * v.x;
+    }
+  }
+}
+
+// Position of the current step k in its checkpoint interval, k - k0 = ic * C + jr,
+// counted down from the window's last step.
+struct CkptPos {
+  int jr = 0, ic = 0;
+  __device__ CkptPos(const DevSys &s, long long k0, long long k1) {
+    if (s.ckpt_every > 0) {
+      jr = (int)(k1 - 1 - k0) % s.ckpt_every;
+      ic = (int)(k1 - 1 - k0) / s.ckpt_every;
+    }
+  }
+};
+
+// After step k: re-sync the state (U_k, stored at k - k0 = ic * C) and count down.
+template <typename T, int Q, int L, int LD>
+__device__ __forceinline__ void ckpt_step(const DevSys &s, int m, const Lane<T, Q, L, LD> &ln, bool state, CkptPos &c,
+                                          double *ur, double *ui) {
+  using G = Geo<T, Q, L, LD>;
+  if (s.ckpt_every <= 0) return;
+  if (c.jr == 0 && c.ic > 0 && state && ln.valid) {
+    const double2 *cp =
+        reinterpret_cast<const double2 *>(s.ckpt) + (((size_t)m * s.ncp + (c.ic - 1)) * s.E + ln.col) * s.N;
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {
+      const double2 v = cp[ln.row(e)];
+      ur[e] = v.x;
+      ui[e] = v.y;
+    }
+  }
+  if (c.jr == 0) {
+    c.jr = s.ckpt_every - 1;
+    --c.ic;
+  } else {
+    --c.jr;
+  }
+}
+
+// The step's 2q inner products of this lane into the wavefront's series buffer; every
+// RB steps, lane i sums one buffered (step, value) row over the 64 lanes in FP64, in
+// lane order, and stores it (idx = k - k0, len = window length).  Only this
+// wavefront touches `red`, and its LDS operations complete in order.
+template <typename T, int Q>
+__device__ __forceinline__ void series_put(T *red, double *ser, int lane, int idx, int len, const T *s1, const T *s2) {
+  using SB = SeriesBuf<T, Q>;
+  T *slot = red + (idx % SB::RB) * SB::RS + lane;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    slot[(2 * j) * SB::VS] = s1[j];
+    slot[(2 * j + 1) * SB::VS] = s2[j];
+  }
+  if (idx % SB::RB == 0) {             // steps idx .. idx+RB-1 are buffered: flush
+    wave_sync();
+    const int r = lane / SB::NV, vv = lane % SB::NV;
+    if (r < SB::RB && idx + r < len) {
+      const T *col = red + r * SB::RS + vv * SB::VS;
+      double acc = 0.0;
+#pragma unroll 8
+      for (int l = 0; l < 64; ++l) acc += (double)col[l];
+      ser[(size_t)(idx + r) * SB::NV + vv] = acc;
+    }
+    wave_sync();
+  }
+}
+
 // Layouts with two or more columns per wavefront (a column spans at most 32 lanes)
 // split the backward sweep's two right-hand sides over the two halves of a
 // wavefront: lanes 0..31 reconstruct the state and lanes 32..63 propagate the
@@ -1175,39 +1272,12 @@ __device__ __forceinline__ void backward_item_split(const DevSys &s, int m, int 
   const bool adj = ln.lane >= 32;                   // this lane's system: state (false) or adjoint (true)
 
   double ar[G::EPL], ai[G::EPL];                    // U (state lanes) or Lambda (adjoint lanes), FP64
-  {
-    const double2 *uf = reinterpret_cast<const double2 *>(s.Ufin) + ((size_t)m * s.E + ln.col) * s.N;
-    const double E2 = (double)s.E * (double)s.E;
-    const double gr = s.scal[4] / E2, gi = s.scal[5] / E2;
-#pragma unroll
-    for (int e = 0; e < G::EPL; ++e) {
-      ar[e] = ai[e] = 0.0;
-      if (!ln.valid) continue;
-      const int r = ln.row(e);
-      const double2 u = uf[r];
-      if (!adj) {
-        ar[e] = u.x;
-        ai[e] = u.y;
-      } else if (m < s.M - 1) {   // mu/2 (W^m - U^m)
-        const double2 w = reinterpret_cast<const double2 *>(s.W)[((size_t)m * s.E + ln.col) * s.N + r];
-        ar[e] = 0.5 * s.mu * (w.x - u.x);
-        ai[e] = 0.5 * s.mu * (w.y - u.y);
-      } else {                    // gamma V / E^2 (the split terminal condition, see backward_item)
-        const double2 v = reinterpret_cast<const double2 *>(s.V)[(size_t)ln.col * s.N + r];
-        ar[e] = gr * v.x - gi * v.y;
-        ai[e] = gr * v.y + gi * v.x;
-      }
-    }
-  }
+  backward_start<T, Q, L, LD>(s, m, ln, adj, ar, ai);
   const long long k0 = s.kstart[m], k1 = s.kstart[m + 1];
   const int kit = kit_of(s);
   const T *ctrl = reinterpret_cast<const T *>(s.ctrl);
   double *ser = s.series + (size_t)item * s.maxlen * 2 * Q;
-  int jr = 0, ic = 0;
-  if (s.ckpt_every > 0) {
-    jr = (int)(k1 - 1 - k0) % s.ckpt_every;
-    ic = (int)(k1 - 1 - k0) / s.ckpt_every;
-  }
+  CkptPos cp(s, k0, k1);
   typename C2<T>::type cnext[Q];
   load_ctrl<T, Q>(ctrl, k1 - 1, cnext);
   for (long long k = k1 - 1; k >= k0; --k) {
@@ -1258,51 +1328,18 @@ __device__ __forceinline__ void backward_item_split(const DevSys &s, int m, int 
     T s1[Q], s2[Q];
     inner_register_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
     inner_lane_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
-    {
-      using SB = SeriesBuf<T, Q>;
-      const int idx = (int)(k - k0);
-      T *slot = red + (idx % SB::RB) * SB::RS + ln.lane;
 #pragma unroll
-      for (int j = 0; j < Q; ++j) {
-        slot[(2 * j) * SB::VS] = adj ? (T)0 : s1[j];
-        slot[(2 * j + 1) * SB::VS] = adj ? (T)0 : s2[j];
-      }
-      if (idx % SB::RB == 0) {             // steps idx .. idx+RB-1 are buffered: flush
-        __syncthreads();
-        const int r = ln.lane / SB::NV, vv = ln.lane % SB::NV;
-        if (r < SB::RB && idx + r < (int)(k1 - k0)) {
-          const T *col = red + r * SB::RS + vv * SB::VS;
-          double acc = 0.0;
-#pragma unroll 8
-          for (int l = 0; l < 64; ++l) acc += (double)col[l];
-          ser[(size_t)(idx + r) * SB::NV + vv] = acc;
-        }
-        __syncthreads();
-      }
+    for (int j = 0; j < Q; ++j) {
+      s1[j] = adj ? (T)0 : s1[j];
+      s2[j] = adj ? (T)0 : s2[j];
     }
+    series_put<T, Q>(red, ser, ln.lane, (int)(k - k0), (int)(k1 - k0), s1, s2);
 #pragma unroll
     for (int e = 0; e < G::EPL; ++e) {
       ar[e] += 2.0 * (double)wr[e];
       ai[e] += 2.0 * (double)wi[e];
     }
-    if (s.ckpt_every > 0) {
-      if (jr == 0 && ic > 0 && !adj && ln.valid) {   // re-sync the state to the stored U_k
-        const double2 *cp =
-            reinterpret_cast<const double2 *>(s.ckpt) + (((size_t)m * s.ncp + (ic - 1)) * s.E + ln.col) * s.N;
-#pragma unroll
-        for (int e = 0; e < G::EPL; ++e) {
-          const double2 c = cp[ln.row(e)];
-          ar[e] = c.x;
-          ai[e] = c.y;
-        }
-      }
-      if (jr == 0) {
-        jr = s.ckpt_every - 1;
-        --ic;
-      } else {
-        --jr;
-      }
-    }
+    ckpt_step<T, Q, L, LD>(s, m, ln, !adj, cp, ar, ai);
   }
   if (!ln.valid || !adj) return;
   double2 *l0 = reinterpret_cast<double2 *>(s.lam0) + ((size_t)m * s.E + ln.col) * s.N;
@@ -1337,39 +1374,13 @@ __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T 
   if constexpr (HOP) ln.init_hop(s);
 
   double udr[G::EPL], udi[G::EPL], ldr[G::EPL], ldi[G::EPL];
-  {
-    const double2 *uf = reinterpret_cast<const double2 *>(s.Ufin) + ((size_t)m * s.E + ln.col) * s.N;
-    const double E2 = (double)s.E * (double)s.E;
-    const double gr = s.scal[4] / E2, gi = s.scal[5] / E2;
-#pragma unroll
-    for (int e = 0; e < G::EPL; ++e) {
-      udr[e] = udi[e] = ldr[e] = ldi[e] = 0.0;
-      if (!ln.valid) continue;
-      const int r = ln.row(e);
-      const double2 u = uf[r];
-      udr[e] = u.x;
-      udi[e] = u.y;
-      if (m < s.M - 1) {          // mu/2 (W^m - U^m)
-        const double2 w = reinterpret_cast<const double2 *>(s.W)[((size_t)m * s.E + ln.col) * s.N + r];
-        ldr[e] = 0.5 * s.mu * (w.x - u.x);
-        ldi[e] = 0.5 * s.mu * (w.y - u.y);
-      } else {                    // gamma V / E^2
-        const double2 v = reinterpret_cast<const double2 *>(s.V)[(size_t)ln.col * s.N + r];
-        ldr[e] = gr * v.x - gi * v.y;
-        ldi[e] = gr * v.y + gi * v.x;
-      }
-    }
-  }
+  backward_start<T, Q, L, LD>(s, m, ln, false, udr, udi);
+  backward_start<T, Q, L, LD>(s, m, ln, true, ldr, ldi);
   const long long k0 = s.kstart[m], k1 = s.kstart[m + 1];
   const int kit = kit_of(s);
   const T *ctrl = reinterpret_cast<const T *>(s.ctrl);
   double *ser = s.series + (size_t)item * s.maxlen * 2 * Q;
-  // position of step k in its checkpoint interval: k - k0 = ic * C + jr
-  int jr = 0, ic = 0;
-  if (s.ckpt_every > 0) {
-    jr = (int)(k1 - 1 - k0) % s.ckpt_every;
-    ic = (int)(k1 - 1 - k0) / s.ckpt_every;
-  }
+  CkptPos cp(s, k0, k1);
 
   for (long long k = k1 - 1; k >= k0; --k) {      // (one column per wavefront: the controls are not loaded ahead)
     typename C2<T>::type ccur[Q];
@@ -1399,28 +1410,7 @@ __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T 
     // A = <y, a_j z> = sum conj(y_r) sqrt(l+1) z_{r+st},  B = <y, a_j^+ z> = sum sqrt(l+1) conj(y_{r+st}) z_r
     inner_register_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
     if constexpr (!fused_inner<T, L>()) inner_lane_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
-    {
-      using SB = SeriesBuf<T, Q>;
-      const int idx = (int)(k - k0);
-      T *slot = red + (idx % SB::RB) * SB::RS + ln.lane;
-#pragma unroll
-      for (int j = 0; j < Q; ++j) {
-        slot[(2 * j) * SB::VS] = s1[j];
-        slot[(2 * j + 1) * SB::VS] = s2[j];
-      }
-      if (idx % SB::RB == 0) {             // steps idx .. idx+RB-1 are buffered: flush
-        __syncthreads();
-        const int r = ln.lane / SB::NV, vv = ln.lane % SB::NV;
-        if (r < SB::RB && idx + r < (int)(k1 - k0)) {
-          const T *col = red + r * SB::RS + vv * SB::VS;
-          double acc = 0.0;
-#pragma unroll 8
-          for (int l = 0; l < 64; ++l) acc += (double)col[l];
-          ser[(size_t)(idx + r) * SB::NV + vv] = acc;
-        }
-        __syncthreads();
-      }
-    }
+    series_put<T, Q>(red, ser, ln.lane, (int)(k - k0), (int)(k1 - k0), s1, s2);
 #pragma unroll
     for (int e = 0; e < G::EPL; ++e) {
       udr[e] += 2.0 * (double)wur[e];
@@ -1428,25 +1418,7 @@ __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T 
       ldr[e] += 2.0 * (double)wlr[e];
       ldi[e] += 2.0 * (double)wli[e];
     }
-    if (s.ckpt_every > 0) {
-      if (jr == 0 && ic > 0) {          // re-sync to the stored U_k, k - k0 = ic * C
-        const double2 *cp =
-            reinterpret_cast<const double2 *>(s.ckpt) + (((size_t)m * s.ncp + (ic - 1)) * s.E + ln.col) * s.N;
-        if (ln.valid)
-#pragma unroll
-          for (int e = 0; e < G::EPL; ++e) {
-            const double2 c = cp[ln.row(e)];
-            udr[e] = c.x;
-            udi[e] = c.y;
-          }
-      }
-      if (jr == 0) {
-        jr = s.ckpt_every - 1;
-        --ic;
-      } else {
-        --jr;
-      }
-    }
+    ckpt_step<T, Q, L, LD>(s, m, ln, true, cp, udr, udi);
   }
   if (!ln.valid) return;
   double2 *l0 = reinterpret_cast<double2 *>(s.lam0) + ((size_t)m * s.E + ln.col) * s.N;
@@ -1483,39 +1455,12 @@ __device__ __forceinline__ void backward_item_xw(const DevSys &s, int m, int cg,
   if constexpr (HOP) ln.init_hop(s);
 
   double ar[G::EPL], ai[G::EPL];                    // U (wavefront 0) or Lambda (wavefront 1), FP64
-  {
-    const double2 *uf = reinterpret_cast<const double2 *>(s.Ufin) + ((size_t)m * s.E + ln.col) * s.N;
-    const double E2 = (double)s.E * (double)s.E;
-    const double gr = s.scal[4] / E2, gi = s.scal[5] / E2;
-#pragma unroll
-    for (int e = 0; e < G::EPL; ++e) {
-      ar[e] = ai[e] = 0.0;
-      if (!ln.valid) continue;
-      const int r = ln.row(e);
-      const double2 u = uf[r];
-      if (wv == 0) {
-        ar[e] = u.x;
-        ai[e] = u.y;
-      } else if (m < s.M - 1) {   // mu/2 (W^m - U^m)
-        const double2 w = reinterpret_cast<const double2 *>(s.W)[((size_t)m * s.E + ln.col) * s.N + r];
-        ar[e] = 0.5 * s.mu * (w.x - u.x);
-        ai[e] = 0.5 * s.mu * (w.y - u.y);
-      } else {                    // gamma V / E^2 (the split terminal condition, see backward_item)
-        const double2 v = reinterpret_cast<const double2 *>(s.V)[(size_t)ln.col * s.N + r];
-        ar[e] = gr * v.x - gi * v.y;
-        ai[e] = gr * v.y + gi * v.x;
-      }
-    }
-  }
+  backward_start<T, Q, L, LD>(s, m, ln, wv == 1, ar, ai);
   const long long k0 = s.kstart[m], k1 = s.kstart[m + 1];
   const int kit = kit_of(s);
   const T *ctrl = reinterpret_cast<const T *>(s.ctrl);
   double *ser = s.series + (size_t)item * s.maxlen * 2 * Q;
-  int jr = 0, ic = 0;
-  if (s.ckpt_every > 0) {
-    jr = (int)(k1 - 1 - k0) % s.ckpt_every;
-    ic = (int)(k1 - 1 - k0) / s.ckpt_every;
-  }
+  CkptPos cp(s, k0, k1);
   for (long long k = k1 - 1; k >= k0; --k) {
     typename C2<T>::type ccur[Q];
     load_ctrl<T, Q>(ctrl, k, ccur);
@@ -1549,50 +1494,14 @@ __device__ __forceinline__ void backward_item_xw(const DevSys &s, int m, int cg,
       T s1[Q], s2[Q];
       inner_register_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
       inner_lane_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
-      using SB = SeriesBuf<T, Q>;
-      const int idx = (int)(k - k0);
-      T *slot = red + (idx % SB::RB) * SB::RS + ln.lane;
-#pragma unroll
-      for (int j = 0; j < Q; ++j) {
-        slot[(2 * j) * SB::VS] = s1[j];
-        slot[(2 * j + 1) * SB::VS] = s2[j];
-      }
-      if (idx % SB::RB == 0) {             // steps idx .. idx+RB-1 are buffered: flush (this wavefront only)
-        wave_sync();
-        const int r = ln.lane / SB::NV, vv = ln.lane % SB::NV;
-        if (r < SB::RB && idx + r < (int)(k1 - k0)) {
-          const T *col = red + r * SB::RS + vv * SB::VS;
-          double acc = 0.0;
-#pragma unroll 8
-          for (int l = 0; l < 64; ++l) acc += (double)col[l];
-          ser[(size_t)(idx + r) * SB::NV + vv] = acc;
-        }
-        wave_sync();
-      }
+      series_put<T, Q>(red, ser, ln.lane, (int)(k - k0), (int)(k1 - k0), s1, s2);
     }
 #pragma unroll
     for (int e = 0; e < G::EPL; ++e) {
       ar[e] += 2.0 * (double)wr[e];
       ai[e] += 2.0 * (double)wi[e];
     }
-    if (s.ckpt_every > 0) {
-      if (jr == 0 && ic > 0 && wv == 0 && ln.valid) {   // re-sync the state to the stored U_k
-        const double2 *cp =
-            reinterpret_cast<const double2 *>(s.ckpt) + (((size_t)m * s.ncp + (ic - 1)) * s.E + ln.col) * s.N;
-#pragma unroll
-        for (int e = 0; e < G::EPL; ++e) {
-          const double2 c = cp[ln.row(e)];
-          ar[e] = c.x;
-          ai[e] = c.y;
-        }
-      }
-      if (jr == 0) {
-        jr = s.ckpt_every - 1;
-        --ic;
-      } else {
-        --jr;
-      }
-    }
+    ckpt_step<T, Q, L, LD>(s, m, ln, wv == 0, cp, ar, ai);
   }
   if (wv == 0 || !ln.valid) return;
   double2 *l0 = reinterpret_cast<double2 *>(s.lam0) + ((size_t)m * s.E + ln.col) * s.N;
