@@ -98,7 +98,7 @@ def bench_batch(seed, reps, log):
     {4,16,64,128}) per qoc_batch_run, FP32 propagation with FP64 accumulation."""
     import numpy as np
     import torch
-    from paper_2407_13950_amd import qoc, workloads as WL
+    from paper_2407_13950_amd import autotune, qoc, workloads as WL
     mix = WL.batch_mix(seed)
     systems, members = [], []
     for e in mix:
@@ -111,6 +111,10 @@ def bench_batch(seed, reps, log):
     b = qoc.Batch(max_contexts=64, max_items=400000)
     b.run(systems)
     torch.cuda.synchronize()
+    # backward schedules of the one-column systems measured on this batch (untimed)
+    tuned = autotune.tune_batch(b, systems, reps=3)
+    log("batch schedule: " + ", ".join(f"{g}: {c}" for g, c in tuned["choice"].items())
+        + f" ({tuned['auto_ms']:.1f} ms by the default rule -> {tuned['tuned_ms']:.1f} ms)")
     t0 = time.perf_counter()
     for _ in range(reps):
         b.run(systems)
@@ -120,7 +124,7 @@ def bench_batch(seed, reps, log):
     same = True
     for idx in (0, 40, 63):
         P_b, _, ga_b, _ = systems[idx].read_results()
-        s2 = qoc.System(members[idx], precision="fp32")
+        s2 = qoc.System(members[idx], precision="fp32", backward_schedule=systems[idx].schedule())
         e = mix[idx]
         s2.set_controls(WL.gen_alpha(members[idx], e["seed"]))
         s2.set_window_states(WL.gen_qr_states(members[idx], e["seed"]))
@@ -131,14 +135,16 @@ def bench_batch(seed, reps, log):
     wsteps = sum(2 * w.n_steps for w in members) * reps
     out = {"evals_per_s": evals / el, "window_steps_per_s": wsteps / el, "ms_per_batch": 1e3 * el / reps,
            "batch": "32x(q2,L3,N_T=4000) + 24x(q3,L4,N_T=20000) + 8x(q4,L4,N_T=100000), M in {4,16,64,128}",
-           "reps": reps, "equal_to_solo_bitwise": bool(same)}
+           "reps": reps, "equal_to_solo_bitwise": bool(same),
+           "schedule": {"choice": tuned["choice"], "default_rule_ms": tuned["auto_ms"],
+                        "tuned_ms": tuned["tuned_ms"], "trials": len(tuned["trials"])}}
     log(f"batched mix: {out['evals_per_s']:.1f} evals/s, {out['ms_per_batch']:.1f} ms per 64-eval batch")
     for s in systems:
         s.close()
     return out
 
 
-def bench_serve(rate, n_requests, plain_requests, seed, budget_gb, log):
+def bench_serve(rate, n_requests, plain_requests, seed, budget_gb, log, schedules=None):
     """Open-loop Poisson trace through the continuous-batching server, and the plain FP64
     per-request path on the first `plain_requests` requests of the same trace."""
     import numpy as np
@@ -146,7 +152,8 @@ def bench_serve(rate, n_requests, plain_requests, seed, budget_gb, log):
     out = {"rate_rps": rate, "requests": n_requests, "runs": 64, "objective_only": 0.1,
            "hbm_budget_GB": budget_gb}
     runs, reqs, counts = serve.make_trace(n_requests, rate=rate, seed=seed, n_runs=64)
-    be = serve.QocBackend(precision="fp32", n_streams=4, max_batch=64, max_items=400000)
+    be = serve.QocBackend(precision="fp32", n_streams=4, max_batch=64, max_items=400000, schedules=schedules)
+    out["backward_schedules"] = dict(schedules or {})
     srv = serve.Server(be, hbm_budget=int(budget_gb * (1 << 30)), max_batch=64)
     for r, w in runs.items():
         srv.register_run(r, w, counts[r], initial=serve.initial_inputs(w, 1000 + r))

@@ -124,6 +124,28 @@ int qoc_get_info(const qoc_ctx *ctx, qoc_info *out);
  * stream).  The caller keeps the stream alive while the context uses it. */
 int qoc_set_stream(qoc_ctx *ctx, void *hip_stream);
 
+/* Schedule of the backward (adjoint) sweep, App. B: a choice of how the work is
+ * spread over wavefronts, not of what is computed.  Two schedules give the same
+ * result up to the rounding order of the per-step inner products.
+ *   QOC_BWD_AUTO      the library's rule (the default): two wavefronts where the
+ *                     layout allows it and the sweep has at most 1024 (window,
+ *                     column group) items, else one;
+ *   QOC_BWD_ONE_WAVE  one wavefront per item reconstructs the state and propagates
+ *                     the adjoint (in the two halves of the wavefront for layouts
+ *                     with two or more columns per wavefront);
+ *   QOC_BWD_TWO_WAVES the state and the adjoint in two wavefronts of one block,
+ *                     handing the state over through LDS each step (layouts with
+ *                     one column per wavefront only, else QOC_EUNSUPPORTED).
+ * The setting belongs to the context and is used by its single and batched calls
+ * alike, so a batched result still equals the single call's bit for bit.
+ * qoc_get_schedule writes the schedule in force with AUTO resolved (ONE_WAVE or
+ * TWO_WAVES).  Errors: QOC_EINVAL (NULL context or output, unknown value). */
+#define QOC_BWD_AUTO 0
+#define QOC_BWD_ONE_WAVE 1
+#define QOC_BWD_TWO_WAVES 2
+int qoc_set_schedule(qoc_ctx *ctx, int32_t backward);
+int qoc_get_schedule(const qoc_ctx *ctx, int32_t *backward);
+
 /* Controls alpha [d] (eq. dj-ctrl and the B-spline expansion).  Copied. */
 int qoc_set_controls(qoc_ctx *ctx, const double *alpha, int64_t d, int32_t where);
 

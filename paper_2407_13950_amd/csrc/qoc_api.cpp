@@ -325,6 +325,22 @@ int qoc_set_stream(qoc_ctx *ctx, void *hip_stream) {
   return QOC_OK;
 }
 
+int qoc_set_schedule(qoc_ctx *ctx, int32_t backward) {
+  if (!ctx) return fail(QOC_EINVAL, "qoc_set_schedule: NULL context");
+  if (backward != QOC_BWD_AUTO && backward != QOC_BWD_ONE_WAVE && backward != QOC_BWD_TWO_WAVES)
+    return fail(QOC_EINVAL, "qoc_set_schedule: unknown backward schedule " + std::to_string(backward));
+  if (backward == QOC_BWD_TWO_WAVES && ctx->dev.cpw != 1)
+    return fail(QOC_EUNSUPPORTED, "qoc_set_schedule: two-wavefront backward needs a one-column-per-wavefront layout");
+  ctx->dev.bwd_sched = backward;
+  return QOC_OK;
+}
+
+int qoc_get_schedule(const qoc_ctx *ctx, int32_t *backward) {
+  if (!ctx || !backward) return fail(QOC_EINVAL, "qoc_get_schedule: NULL argument");
+  *backward = qoc::xw_backward(ctx->dev) ? QOC_BWD_TWO_WAVES : QOC_BWD_ONE_WAVE;
+  return QOC_OK;
+}
+
 static hipMemcpyKind kind_in(int32_t where) { return where == QOC_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice; }
 static hipMemcpyKind kind_out(int32_t where) { return where == QOC_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost; }
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "../../include/qoc.h"
+
 namespace qoc {
 
 // Everything one evaluation needs on the device, as plain pointers and sizes.
@@ -29,6 +31,7 @@ struct DevSys {
   int ckpt_every;           // checkpoint spacing in steps (0 = none)
   int ncp;                  // checkpoints stored per window
   int kit_fixed;            // > 0: fixed-point iterations forced by the caller
+  int bwd_sched;            // backward-sweep schedule: QOC_BWD_AUTO, _ONE_WAVE or _TWO_WAVES
   double solve_tol;         // per-step truncation target of the fixed point
 
   const long long *kstart;  // [M+1] first step of each window (floor split)
@@ -78,13 +81,17 @@ int launch_phase(const DevSys &s, int phase, hipStream_t st, double *Wout = null
 // over all (system, window, column group) items, each small kernel as one launch
 // over a (system, block) table.  All systems share the precision `fp64`.
 // The backward sweep of a one-column-per-wavefront layout runs as two wavefronts per
-// (window, column group), state and adjoint, when the launch has at most one
-// wavefront per SIMD otherwise (1024 SIMDs).  A function of the system alone, so a
-// batched evaluation makes the same choice as a solo one.
+// (window, column group), state and adjoint, when the caller asks for it or, by
+// default, when the launch has at most one wavefront per SIMD otherwise (1024
+// SIMDs).  A function of the system and its schedule setting alone, so a batched
+// evaluation makes the same choice as a solo one.
 #ifndef QOC_XW_MAX_ITEMS
 #define QOC_XW_MAX_ITEMS 1024
 #endif
-inline bool xw_backward(const DevSys &s) { return s.cpw == 1 && (long long)s.M * s.ncg_b <= QOC_XW_MAX_ITEMS; }
+inline bool xw_backward(const DevSys &s) {
+  if (s.cpw != 1 || s.bwd_sched == QOC_BWD_ONE_WAVE) return false;
+  return s.bwd_sched == QOC_BWD_TWO_WAVES || (long long)s.M * s.ncg_b <= QOC_XW_MAX_ITEMS;
+}
 
 struct BatchPlan {
   const DevSys *sys;              // [n] device copy of the systems

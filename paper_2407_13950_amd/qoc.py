@@ -27,12 +27,15 @@ LIB_PATH = os.path.join(HERE, "libqoc.so")
 QOC_OK, QOC_EINVAL, QOC_ENOMEM, QOC_EDEVICE, QOC_ENOTCONV, QOC_EUNSUPPORTED, QOC_ESTATE = 0, -1, -2, -3, -4, -5, -6
 QOC_HOST, QOC_DEVICE = 0, 1
 QOC_FP64, QOC_FP32 = 0, 1
+QOC_BWD_AUTO, QOC_BWD_ONE_WAVE, QOC_BWD_TWO_WAVES = 0, 1, 2
+SCHEDULES = {"auto": QOC_BWD_AUTO, "one_wave": QOC_BWD_ONE_WAVE, "two_waves": QOC_BWD_TWO_WAVES}
 
 EXPORTED = ["qoc_create", "qoc_destroy", "qoc_get_info", "qoc_set_stream", "qoc_set_controls",
             "qoc_set_window_states", "qoc_objective", "qoc_gradient", "qoc_rollout", "qoc_synchronize",
             "qoc_last_error", "qoc_strerror", "qoc_enable_timing", "qoc_get_timings", "qoc_backward",
             "qoc_batch_create", "qoc_batch_destroy", "qoc_batch_run", "qoc_read_results",
-            "qoc_opt_create", "qoc_opt_destroy", "qoc_opt_run", "qoc_opt_get"]
+            "qoc_opt_create", "qoc_opt_destroy", "qoc_opt_run", "qoc_opt_get", "qoc_set_schedule",
+            "qoc_get_schedule"]
 
 PHASES = ["controls", "forward", "boundary", "backward", "project", "grad_W", "total"]
 
@@ -116,6 +119,8 @@ def load_library(path: str = LIB_PATH):
         "qoc_opt_destroy": ([vp], ctypes.c_int),
         "qoc_opt_run": ([vp, i32, ctypes.POINTER(OptStatus)], ctypes.c_int),
         "qoc_opt_get": ([vp, vp, vp, i32], ctypes.c_int),
+        "qoc_set_schedule": ([vp, i32], ctypes.c_int),
+        "qoc_get_schedule": ([vp, ctypes.POINTER(i32)], ctypes.c_int),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -152,7 +157,7 @@ class System:
     """One system/context: qoc_create .. qoc_destroy."""
 
     def __init__(self, w, precision: str = "fp32", fixed_point_iters: int = 0, solve_tol: float = 0.0,
-                 checkpoint_every: Optional[int] = None, device: int = 0):
+                 checkpoint_every: Optional[int] = None, device: int = 0, backward_schedule: str = "auto"):
         lib = load_library()
         self.w = w
         self._keep = [np.ascontiguousarray(w.detuning, dtype=np.float64),
@@ -176,6 +181,8 @@ class System:
         _check(lib.qoc_get_info(self.h, ctypes.byref(inf)))
         self.info = {f: getattr(inf, f) for f, _ in Info._fields_}
         self.N, self.E, self.d, self.M = inf.N, inf.E, inf.d, inf.n_windows
+        if backward_schedule != "auto":
+            self.set_schedule(backward_schedule)
 
     def close(self):
         if getattr(self, "h", None) and self.h.value:
@@ -298,6 +305,22 @@ class System:
 
     def enable_timing(self, on: bool = True):
         _check(_lib.qoc_enable_timing(self.h, 1 if on else 0))
+
+    def set_schedule(self, backward: str = "auto"):
+        """Backward-sweep schedule: "auto", "one_wave" or "two_waves" (qoc_set_schedule)."""
+        if backward not in SCHEDULES:
+            raise ValueError(f"unknown backward schedule {backward!r}; expected one of {sorted(SCHEDULES)}")
+        _check(_lib.qoc_set_schedule(self.h, SCHEDULES[backward]))
+
+    def schedule(self) -> str:
+        """The backward schedule in force, with "auto" resolved."""
+        v = ctypes.c_int32()
+        _check(_lib.qoc_get_schedule(self.h, ctypes.byref(v)))
+        return {QOC_BWD_ONE_WAVE: "one_wave", QOC_BWD_TWO_WAVES: "two_waves"}[v.value]
+
+    def schedules(self):
+        """The backward schedules this system's layout offers."""
+        return ["one_wave", "two_waves"] if self.info["columns_per_wave"] == 1 else ["one_wave"]
 
     def timings(self):
         """Mean kernel ms per phase over the evaluations recorded since enable_timing()."""

@@ -223,11 +223,12 @@ class QocBackend(Backend):
     """Runs batches through the C ABI: one qoc_batch per stream, one qoc context per run."""
 
     def __init__(self, precision: str = "fp32", n_streams: int = 4, max_batch: int = 64, max_items: int = 400000,
-                 keep_results: bool = False):
+                 keep_results: bool = False, schedules: Optional[Dict[str, str]] = None):
         import torch
-        from . import qoc
-        self.torch, self.qoc = torch, qoc
+        from . import autotune, qoc
+        self.torch, self.qoc, self.autotune = torch, qoc, autotune
         self.precision = precision
+        self.schedules = schedules or {}        # backward schedule per system group (autotune.group_key)
         self._streams = [torch.cuda.Stream() for _ in range(n_streams)]   # default priority
         self._batches = [qoc.Batch(max_batch, max_items) for _ in range(n_streams)]
         self.keep_results = keep_results
@@ -254,6 +255,7 @@ class QocBackend(Backend):
         torch = self.torch
         alpha0, W0 = initial
         s = self.qoc.System(w, precision=self.precision)
+        self.autotune.apply([s], self.schedules)
         h = {"system": s, "w": w, "alpha": torch.as_tensor(alpha0, device="cuda").clone(),
              "W": None, "g_alpha": None, "g_W": None}
         if w.n_windows > 1:

@@ -117,5 +117,8 @@ def test_null_arguments_are_errors():
     assert lib.qoc_gradient(None, None, None, None, None, 0) == qoc.QOC_EINVAL
     assert lib.qoc_set_controls(None, None, 0, 0) == qoc.QOC_EINVAL
     assert lib.qoc_destroy(None) == qoc.QOC_OK
+    assert lib.qoc_set_schedule(None, qoc.QOC_BWD_AUTO) == qoc.QOC_EINVAL
+    v = ctypes.c_int32(-9)
+    assert lib.qoc_get_schedule(None, ctypes.byref(v)) == qoc.QOC_EINVAL and v.value == -9
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert lib.qoc_strerror(code)
