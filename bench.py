@@ -137,7 +137,7 @@ def bench_batch(seed, reps, log):
            "batch": "32x(q2,L3,N_T=4000) + 24x(q3,L4,N_T=20000) + 8x(q4,L4,N_T=100000), M in {4,16,64,128}",
            "reps": reps, "equal_to_solo_bitwise": bool(same),
            "schedule": {"choice": tuned["choice"], "default_rule_ms": tuned["auto_ms"],
-                        "tuned_ms": tuned["tuned_ms"], "trials": len(tuned["trials"])}}
+                        "tuned_ms": tuned["tuned_ms"], "trials": tuned["trials"]}}
     log(f"batched mix: {out['evals_per_s']:.1f} evals/s, {out['ms_per_batch']:.1f} ms per 64-eval batch")
     for s in systems:
         s.close()

@@ -127,22 +127,28 @@ int qoc_set_stream(qoc_ctx *ctx, void *hip_stream);
 /* Schedule of the backward (adjoint) sweep, App. B: a choice of how the work is
  * spread over wavefronts, not of what is computed.  Two schedules give the same
  * result up to the rounding order of the per-step inner products.
- *   QOC_BWD_AUTO      the library's rule (the default): two wavefronts where the
- *                     layout allows it and the sweep has at most 1024 (window,
- *                     column group) items, else one;
- *   QOC_BWD_ONE_WAVE  one wavefront per item reconstructs the state and propagates
- *                     the adjoint (in the two halves of the wavefront for layouts
- *                     with two or more columns per wavefront);
- *   QOC_BWD_TWO_WAVES the state and the adjoint in two wavefronts of one block,
- *                     handing the state over through LDS each step (layouts with
- *                     one column per wavefront only, else QOC_EUNSUPPORTED).
- * The setting belongs to the context and is used by its single and batched calls
- * alike, so a batched result still equals the single call's bit for bit.
- * qoc_get_schedule writes the schedule in force with AUTO resolved (ONE_WAVE or
- * TWO_WAVES).  Errors: QOC_EINVAL (NULL context or output, unknown value). */
+ *   QOC_BWD_AUTO        the library's rule (the default): three wavefronts where
+ *                       the layout allows it and the sweep has at most 1024 (FP32)
+ *                       or 256 (FP64) (window, column group) items, else one;
+ *   QOC_BWD_ONE_WAVE    one wavefront per item reconstructs the state and
+ *                       propagates the adjoint (in the two halves of the wavefront
+ *                       for layouts with two or more columns per wavefront);
+ *   QOC_BWD_TWO_WAVES   the state and the adjoint in two wavefronts of one block,
+ *                       handing the state over through LDS each step;
+ *   QOC_BWD_THREE_WAVES as TWO_WAVES, plus a third wavefront that takes the
+ *                       per-step inner products from both solutions, one step
+ *                       behind, so that a step costs the solving wavefronts one
+ *                       solve (for long windows on an otherwise idle GPU).
+ * TWO_WAVES and THREE_WAVES need a layout with one column per wavefront, else
+ * QOC_EUNSUPPORTED.  The setting belongs to the context and is used by its single
+ * and batched calls alike, so a batched result still equals the single call's bit
+ * for bit.  qoc_get_schedule writes the schedule in force with AUTO resolved
+ * (ONE_WAVE, TWO_WAVES or THREE_WAVES).  Errors: QOC_EINVAL (NULL context or
+ * output, unknown value). */
 #define QOC_BWD_AUTO 0
 #define QOC_BWD_ONE_WAVE 1
 #define QOC_BWD_TWO_WAVES 2
+#define QOC_BWD_THREE_WAVES 3
 int qoc_set_schedule(qoc_ctx *ctx, int32_t backward);
 int qoc_get_schedule(const qoc_ctx *ctx, int32_t *backward);
 
@@ -198,10 +204,10 @@ int qoc_rollout(qoc_ctx *ctx, double *W_out, double *U_out, int32_t where);
  * QOC_EINVAL (mixed precision/device, duplicates, more contexts or items than
  * the batch was created for), QOC_ESTATE (a context without controls/states).
  * Results agree with the single-context calls bit for bit (same kernels, same
- * reduction order).  The backward sweeps of 4-qubit 4-level contexts with at most
- * 64 windows (two wavefronts per item) run on a stream the batch owns, forked from
- * hip_stream and joined back to it within the call's work, so the caller sees
- * ordinary stream order.  max_items bounds the forward items and, separately, the
+ * reduction order).  Backward sweeps of two and of three wavefronts per item
+ * (qoc_set_schedule) run on two streams the batch owns, forked from hip_stream and
+ * joined back to it within the call's work, so the caller sees ordinary stream
+ * order.  max_items bounds the forward items and, separately, the
  * backward items (window x backward column group) of one call. */
 typedef struct qoc_batch qoc_batch;
 int qoc_batch_create(int32_t device, int32_t max_contexts, int64_t max_items, qoc_batch **out);

@@ -2,21 +2,23 @@
 
 The adjoint sweep of App. B can spread its work over wavefronts in more than one
 way (one wavefront per (window, column group) carrying the state reconstruction
-and the adjoint, or two wavefronts per item, one for each, on layouts with one
-column per wavefront).  Which is faster depends on how many items share the GPU:
-two wavefronts shorten a window's chain of steps, one wavefront spends fewer
-instructions per item-step.  The library's default rule uses the item count of
-the launch; the functions here measure instead.
+and the adjoint; or, on layouts with one column per wavefront, two wavefronts per
+item, one for each, or three, the third taking the per-step inner products).  Which is faster depends on how many items share the GPU:
+two or three wavefronts shorten a window's chain of steps, one wavefront spends
+fewer instructions per item-step.  The library's default rule uses the item count
+of the launch; the functions here measure instead.
 
 * `tune_system`: times the backward phase of one system under each schedule its
   layout offers (the library's own HIP events, mean over `reps` gradient calls
   after warm-up) and keeps the fastest.
 * `tune_batch`: a batched evaluation's makespan depends on all of its members,
   so the candidates are timed on the batch itself.  Tunable systems are grouped
-  by (qubits, levels, windows, steps, dipole); starting from the default rule,
-  each group in turn is switched to every other schedule while the rest stay as
-  they are, and a switch is kept when it shortens the batch by more than
-  `min_gain` (one pass of coordinate descent).
+  by (qubits, levels, windows, steps, dipole, precision).  The makespan is a
+  maximum over the members' chains, so moving one group alone often changes
+  nothing; the tuner first tries every schedule for all groups at once against
+  the default rule, keeps the best, and then switches each group in turn to every
+  other schedule while the rest stay as they are (one pass of coordinate descent).
+  A move is kept when it shortens the batch by more than `min_gain`.
 
 A schedule is a property of the context, used by its single and batched calls
 alike, so a tuned batch still returns each member's single-call result bit for
@@ -87,7 +89,22 @@ def tune_batch(batch, systems: Sequence, reps: int = 3, want_grad: Optional[Sequ
     best_ms = _time_batch(batch, systems, reps, want_grad)
     auto_ms = best_ms
     trials = [{"assignment": dict(current), "ms": best_ms}]
+    offered = sorted({c for members in groups.values() for c in members[0].schedules()})
+    for cand in offered:                                          # joint moves: every group at once
+        assign = {g: cand for g in groups}
+        if assign == current:
+            continue
+        for g, members in groups.items():
+            for s in members:
+                s.set_schedule(cand)
+        ms = _time_batch(batch, systems, reps, want_grad)
+        trials.append({"assignment": dict(assign), "ms": ms})
+        if ms < best_ms * (1.0 - min_gain):
+            best_ms, current = ms, assign
     for g, members in groups.items():
+        for s in members:
+            s.set_schedule(current[g])
+    for g, members in groups.items():                             # then one group at a time
         start = current[g]
         for cand in members[0].schedules():
             if cand == start:

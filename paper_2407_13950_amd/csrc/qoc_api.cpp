@@ -327,17 +327,20 @@ int qoc_set_stream(qoc_ctx *ctx, void *hip_stream) {
 
 int qoc_set_schedule(qoc_ctx *ctx, int32_t backward) {
   if (!ctx) return fail(QOC_EINVAL, "qoc_set_schedule: NULL context");
-  if (backward != QOC_BWD_AUTO && backward != QOC_BWD_ONE_WAVE && backward != QOC_BWD_TWO_WAVES)
+  if (backward != QOC_BWD_AUTO && backward != QOC_BWD_ONE_WAVE && backward != QOC_BWD_TWO_WAVES &&
+      backward != QOC_BWD_THREE_WAVES)
     return fail(QOC_EINVAL, "qoc_set_schedule: unknown backward schedule " + std::to_string(backward));
-  if (backward == QOC_BWD_TWO_WAVES && ctx->dev.cpw != 1)
-    return fail(QOC_EUNSUPPORTED, "qoc_set_schedule: two-wavefront backward needs a one-column-per-wavefront layout");
+  if ((backward == QOC_BWD_TWO_WAVES || backward == QOC_BWD_THREE_WAVES) && ctx->dev.cpw != 1)
+    return fail(QOC_EUNSUPPORTED, "qoc_set_schedule: a backward of two or three wavefronts needs a "
+                                  "one-column-per-wavefront layout");
   ctx->dev.bwd_sched = backward;
   return QOC_OK;
 }
 
 int qoc_get_schedule(const qoc_ctx *ctx, int32_t *backward) {
   if (!ctx || !backward) return fail(QOC_EINVAL, "qoc_get_schedule: NULL argument");
-  *backward = qoc::xw_backward(ctx->dev) ? QOC_BWD_TWO_WAVES : QOC_BWD_ONE_WAVE;
+  const int waves = qoc::bwd_waves(ctx->dev);
+  *backward = waves == 3 ? QOC_BWD_THREE_WAVES : waves == 2 ? QOC_BWD_TWO_WAVES : QOC_BWD_ONE_WAVE;
   return QOC_OK;
 }
 
@@ -538,12 +541,15 @@ struct qoc_batch {
   hipEvent_t uploaded = nullptr; // staging may be rewritten once this has passed
   bool pending = false;
   hipStream_t aux = nullptr;      // backward items of two wavefronts run here (default priority)
-  hipEvent_t fork = nullptr, join = nullptr;
+  hipStream_t aux2 = nullptr;     // backward items of three wavefronts run here (default priority)
+  hipEvent_t fork = nullptr, join = nullptr, join2 = nullptr;
   ~qoc_batch() {
     if (uploaded) { (void)hipEventSynchronize(uploaded); (void)hipEventDestroy(uploaded); }
     if (aux) { (void)hipStreamSynchronize(aux); (void)hipStreamDestroy(aux); }
+    if (aux2) { (void)hipStreamSynchronize(aux2); (void)hipStreamDestroy(aux2); }
     if (fork) (void)hipEventDestroy(fork);
     if (join) (void)hipEventDestroy(join);
+    if (join2) (void)hipEventDestroy(join2);
     (void)hipFree(d_sys); (void)hipFree(d_items); (void)hipFree(d_blocks);
     (void)hipHostFree(h_stage);
   }
@@ -567,6 +573,8 @@ int qoc_batch_create(int32_t device, int32_t max_contexts, int64_t max_items, qo
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->aux2, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join2, hipEventDisableTiming);
   if (e != hipSuccess) { delete b; return fail(QOC_ENOMEM, std::string("qoc_batch_create: ") + hipGetErrorString(e)); }
   *out = b;
   return QOC_OK;
@@ -596,7 +604,7 @@ int qoc_batch_run(qoc_batch *b, qoc_ctx *const *ctxs, int32_t n, const int32_t *
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   // propagation items, longest first (cost ~ steps x entries per lane x qubits)
   struct It { long long cost; int4 v; };
-  std::vector<It> fwd, bwd, xw;
+  std::vector<It> fwd, bwd, xw, x3;
   long long nblocks = 0;
   for (int i = 0; i < n; ++i) {
     const qoc_ctx *c = ctxs[i];
@@ -608,9 +616,10 @@ int qoc_batch_run(qoc_batch *b, qoc_ctx *const *ctxs, int32_t n, const int32_t *
       len = (long long)(((__int128)(m + 1) * c->NT) / c->M) - (long long)(((__int128)m * c->NT) / c->M);
       for (int cg = 0; cg < c->dev.ncg; ++cg) fwd.push_back({len * per_lane * c->q, make_int4(i, m, cg, c->shape)});
       if (g) {
-        const bool two = qoc::xw_backward(c->dev);                                      // two wavefronts per item
-        const long long bcost = (c->dev.cpw >= 2 || two ? 1 : 2) * len * per_lane * c->q;   // one system per lane
-        for (int cg = 0; cg < c->dev.ncg_b; ++cg) (two ? xw : bwd).push_back({bcost, make_int4(i, m, cg, c->shape)});
+        const int waves = qoc::bwd_waves(c->dev);                                        // wavefronts per item
+        const long long bcost = (c->dev.cpw >= 2 || waves > 1 ? 1 : 2) * len * per_lane * c->q;   // one system per lane
+        std::vector<It> &dst = waves == 3 ? x3 : waves == 2 ? xw : bwd;
+        for (int cg = 0; cg < c->dev.ncg_b; ++cg) dst.push_back({bcost, make_int4(i, m, cg, c->shape)});
       }
     }
     for (int k = 0; k < qoc::SK_COUNT; ++k) {
@@ -618,13 +627,14 @@ int qoc_batch_run(qoc_batch *b, qoc_ctx *const *ctxs, int32_t n, const int32_t *
       if (!gk || g) nblocks += qoc::small_blocks(c->dev, k);
     }
   }
-  if ((long long)fwd.size() > b->max_items || (long long)(bwd.size() + xw.size()) > b->max_items)
+  if ((long long)fwd.size() > b->max_items || (long long)(bwd.size() + xw.size() + x3.size()) > b->max_items)
     return fail(QOC_EINVAL, "qoc_batch_run: more propagation items than the batch was created for");
   if (nblocks > b->max_blocks) return fail(QOC_EINVAL, "qoc_batch_run: small-kernel table exceeds the batch capacity");
   auto by_cost = [](const It &x, const It &y) { return x.cost > y.cost; };
   std::stable_sort(fwd.begin(), fwd.end(), by_cost);
   std::stable_sort(bwd.begin(), bwd.end(), by_cost);
   std::stable_sort(xw.begin(), xw.end(), by_cost);
+  std::stable_sort(x3.begin(), x3.end(), by_cost);
 
   // the previous run's uploads must have left the staging buffer
   if (b->pending) HIP_OR_RETURN(hipEventSynchronize(b->uploaded));
@@ -636,18 +646,23 @@ int qoc_batch_run(qoc_batch *b, qoc_ctx *const *ctxs, int32_t n, const int32_t *
   for (size_t k = 0; k < fwd.size(); ++k) hi[k] = fwd[k].v;
   for (size_t k = 0; k < bwd.size(); ++k) hi[fwd.size() + k] = bwd[k].v;
   for (size_t k = 0; k < xw.size(); ++k) hi[fwd.size() + bwd.size() + k] = xw[k].v;
+  for (size_t k = 0; k < x3.size(); ++k) hi[fwd.size() + bwd.size() + xw.size() + k] = x3[k].v;
   qoc::BatchPlan plan{};
   plan.fp64 = fp64;
   plan.sys = b->d_sys;
   plan.fwd_items = b->d_items;
   plan.bwd_items = b->d_items + fwd.size();
   plan.xw_items = b->d_items + fwd.size() + bwd.size();
+  plan.x3_items = b->d_items + fwd.size() + bwd.size() + xw.size();
   plan.n_fwd = (int)fwd.size();
   plan.n_bwd = (int)bwd.size();
   plan.n_xw = (int)xw.size();
+  plan.n_x3 = (int)x3.size();
   plan.aux = b->aux;
+  plan.aux2 = b->aux2;
   plan.fork = b->fork;
   plan.join = b->join;
+  plan.join2 = b->join2;
   long long off = 0;
   for (int k = 0; k < qoc::SK_COUNT; ++k) {
     const bool gk = k == qoc::SK_SERIES || k == qoc::SK_PROJECT || k == qoc::SK_GRADW;
@@ -662,7 +677,7 @@ int qoc_batch_run(qoc_batch *b, qoc_ctx *const *ctxs, int32_t n, const int32_t *
     off += cnt;
   }
   HIP_OR_RETURN(hipMemcpyAsync(b->d_sys, hs, sizeof(qoc::DevSys) * n, hipMemcpyHostToDevice, st));
-  HIP_OR_RETURN(hipMemcpyAsync(b->d_items, hi, sizeof(int4) * (fwd.size() + bwd.size() + xw.size()),
+  HIP_OR_RETURN(hipMemcpyAsync(b->d_items, hi, sizeof(int4) * (fwd.size() + bwd.size() + xw.size() + x3.size()),
                                hipMemcpyHostToDevice, st));
   HIP_OR_RETURN(hipMemcpyAsync(b->d_blocks, hb, sizeof(int2) * std::max<long long>(off, 1), hipMemcpyHostToDevice, st));
   HIP_OR_RETURN(hipEventRecord(b->uploaded, st));

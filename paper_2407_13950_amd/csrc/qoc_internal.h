@@ -80,27 +80,36 @@ int launch_phase(const DevSys &s, int phase, hipStream_t st, double *Wout = null
 // Several systems evaluated together: the propagation phases run as one launch
 // over all (system, window, column group) items, each small kernel as one launch
 // over a (system, block) table.  All systems share the precision `fp64`.
-// The backward sweep of a one-column-per-wavefront layout runs as two wavefronts per
-// (window, column group), state and adjoint, when the caller asks for it or, by
-// default, when the launch has at most one wavefront per SIMD otherwise (1024
-// SIMDs).  A function of the system and its schedule setting alone, so a batched
-// evaluation makes the same choice as a solo one.
-#ifndef QOC_XW_MAX_ITEMS
-#define QOC_XW_MAX_ITEMS 1024
+// Wavefronts per backward item (1, 2 or 3; more than one only for layouts with one
+// column per wavefront): the caller's schedule, or by default three (state, adjoint,
+// inner products) when the launch would otherwise leave SIMDs idle -- at most 1024
+// items (one wavefront per SIMD) in FP32, 256 in FP64, whose solving wavefronts need
+// more registers -- and one otherwise.  Two wavefronts (state and adjoint, the inner
+// products on the adjoint's chain) only on request.  A function of the system and its
+// schedule setting alone, so a batched evaluation makes the same choice as a solo one.
+#ifndef QOC_X3_MAX_ITEMS_FP32
+#define QOC_X3_MAX_ITEMS_FP32 1024
 #endif
-inline bool xw_backward(const DevSys &s) {
-  if (s.cpw != 1 || s.bwd_sched == QOC_BWD_ONE_WAVE) return false;
-  return s.bwd_sched == QOC_BWD_TWO_WAVES || (long long)s.M * s.ncg_b <= QOC_XW_MAX_ITEMS;
+#ifndef QOC_X3_MAX_ITEMS_FP64
+#define QOC_X3_MAX_ITEMS_FP64 256
+#endif
+inline int bwd_waves(const DevSys &s) {
+  if (s.cpw != 1 || s.bwd_sched == QOC_BWD_ONE_WAVE) return 1;
+  if (s.bwd_sched == QOC_BWD_TWO_WAVES) return 2;
+  if (s.bwd_sched == QOC_BWD_THREE_WAVES) return 3;
+  const long long items = (long long)s.M * s.ncg_b;
+  return items <= (s.fp64 ? QOC_X3_MAX_ITEMS_FP64 : QOC_X3_MAX_ITEMS_FP32) ? 3 : 1;
 }
 
 struct BatchPlan {
   const DevSys *sys;              // [n] device copy of the systems
   const int4 *fwd_items;          // [n_fwd] (system, window, column group, shape), longest first
   const int4 *bwd_items;          // [n_bwd]
-  const int4 *xw_items;           // [n_xw] backward items of xw_backward systems (two wavefronts each)
-  int n_fwd, n_bwd, n_xw;
-  hipStream_t aux;                // the xw items run here, forked from and joined to the caller's stream
-  hipEvent_t fork, join;
+  const int4 *xw_items;           // [n_xw] backward items of two wavefronts each (bwd_waves == 2)
+  const int4 *x3_items;           // [n_x3] backward items of three wavefronts each (bwd_waves == 3)
+  int n_fwd, n_bwd, n_xw, n_x3;
+  hipStream_t aux, aux2;          // the xw and x3 items run there, forked from and joined to the caller's stream
+  hipEvent_t fork, join, join2;
   const int2 *blocks[SK_COUNT];   // per small kernel: (system, block within the system)
   int n_blocks[SK_COUNT];
   int fp64;

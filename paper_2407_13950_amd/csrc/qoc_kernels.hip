@@ -1532,6 +1532,108 @@ __device__ __forceinline__ void xw_item(const DevSys &s, int m, int cg, T *red, 
   if constexpr (Geo<T, Q, L, LD>::CPW == 1) backward_item_xw<T, Q, L, LD, HOP>(s, m, cg, red, xb, zb);
 }
 
+// Three wavefronts per (window, column group) for the one-column-per-wavefront layout,
+// for launches whose windows are long chains on an otherwise idle GPU: wavefront 0
+// reconstructs the state, wavefront 1 propagates the adjoint, and each leaves its step
+// solution (z or y) in a double-buffered LDS record; in the next iteration wavefront 2
+// reads both records and takes that step's inner products while 0 and 1 solve the
+// following step.  The inner products thus leave the solving wavefronts' chain: a step
+// costs one solve and one barrier.  The loop runs one iteration more than the window
+// has steps and ends every iteration with the block barrier, outside the role branches.
+// A record of step k is rewritten (for step k-2) only in the iteration after the one in
+// which wavefront 2 read it, i.e. after a barrier.
+template <typename T, int Q, int L, int LD, bool HOP>
+__device__ __forceinline__ void backward_item_x3(const DevSys &s, int m, int cg, T *red, T *xb, T *zb, T *yb) {
+  using G = Geo<T, Q, L, LD>;
+  constexpr int RS = 64 * 2 * G::EPL;               // elements of one step's record
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // 0: state, 1: adjoint, 2: inner products
+  const int item = m * s.ncg_b + cg;
+  Lane<T, Q, L, LD> ln;
+  ln.init(s, cg, xb);
+  if constexpr (HOP) {
+    if (wv < 2) ln.init_hop(s);
+  }
+  const long long k0 = s.kstart[m], k1 = s.kstart[m + 1];
+  const int roff = ln.lane * 2 * G::EPL;
+  double ar[G::EPL], ai[G::EPL];                    // U (wavefront 0) or Lambda (wavefront 1), FP64
+  if (wv < 2) backward_start<T, Q, L, LD>(s, m, ln, wv == 1, ar, ai);
+  const int kit = kit_of(s);
+  const T *ctrl = reinterpret_cast<const T *>(s.ctrl);
+  double *ser = s.series + (size_t)item * s.maxlen * 2 * Q;
+  T *own = (wv == 0 ? zb : yb) + roff;
+  CkptPos cp(s, k0, k1);
+  for (long long k = k1 - 1; k >= k0 - 1; --k) {
+    if (wv < 2 && k >= k0) {                        // solve step k, leave z or y in record k & 1
+      typename C2<T>::type ccur[Q];
+      load_ctrl<T, Q>(ctrl, k, ccur);
+      Coef<T, Q, L, LD> cf;
+      step_coeffs<T, Q, L, LD>(ln, ccur, cf);
+      T ur[G::EPL], ui[G::EPL], wr[G::EPL], wi[G::EPL];
+#pragma unroll
+      for (int e = 0; e < G::EPL; ++e) {
+        ur[e] = (T)ar[e];
+        ui[e] = (T)ai[e];
+      }
+      solve_increment<T, Q, L, LD, true, HOP>(ln, kit, cf, ur, ui, wr, wi);
+      T *rec = own + (size_t)(k & 1) * RS;
+#pragma unroll
+      for (int e = 0; e < G::EPL; ++e) {
+        rec[2 * e] = ur[e] + wr[e];
+        rec[2 * e + 1] = ui[e] + wi[e];
+        ar[e] += 2.0 * (double)wr[e];
+        ai[e] += 2.0 * (double)wi[e];
+      }
+      ckpt_step<T, Q, L, LD>(s, m, ln, wv == 0, cp, ar, ai);
+    }
+    if (wv == 2 && k < k1 - 1) {                    // inner products of step k + 1 (records of the last iteration)
+      const long long kp = k + 1;
+      const T *zrec = zb + (size_t)(kp & 1) * RS + roff;
+      const T *yrec = yb + (size_t)(kp & 1) * RS + roff;
+      T zr[G::EPL], zi[G::EPL], yr[G::EPL], yi[G::EPL];
+#pragma unroll
+      for (int e = 0; e < G::EPL; ++e) {
+        zr[e] = zrec[2 * e];
+        zi[e] = zrec[2 * e + 1];
+        yr[e] = yrec[2 * e];
+        yi[e] = yrec[2 * e + 1];
+      }
+      T s1[Q], s2[Q];
+      inner_register_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
+      inner_lane_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
+      series_put<T, Q>(red, ser, ln.lane, (int)(kp - k0), (int)(k1 - k0), s1, s2);
+    }
+    __syncthreads();                                // every wavefront, every iteration
+  }
+  if (wv != 1 || !ln.valid) return;
+  double2 *l0 = reinterpret_cast<double2 *>(s.lam0) + ((size_t)m * s.E + ln.col) * s.N;
+#pragma unroll
+  for (int e = 0; e < G::EPL; ++e) l0[ln.row(e)] = double2{ar[e], ai[e]};
+}
+
+// Per block: three exchange buffers, the double-buffered z and y records, and
+// wavefront 2's series buffer.
+template <typename T, bool HOP>
+constexpr int x3_lds_elems() { return 3 * (xchg_bytes<T, HOP>() / (int)sizeof(T)) + 4 * 64 * 8 + red_elems<T>(); }
+
+template <typename T, int Q, int L, int LD, bool HOP>
+__global__ __launch_bounds__(192) void k_backward_x3(DevSys s, int nitems) {
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  if (item >= nitems) return;                       // uniform over the block
+  __shared__ __align__(16) T lds[x3_lds_elems<T, HOP>()];
+  constexpr int XE = xchg_bytes<T, HOP>() / (int)sizeof(T);
+  T *xb = lds + (threadIdx.x >> 6) * XE;
+  T *zb = lds + 3 * XE;
+  T *yb = zb + 2 * 64 * 8;
+  T *red = yb + 2 * 64 * 8;
+  xchg_clear<T, HOP>(xb);
+  backward_item_x3<T, Q, L, LD, HOP>(s, item / s.ncg_b, item % s.ncg_b, red, xb, zb, yb);
+}
+
+template <typename T, int Q, int L, int LD, bool HOP>
+__device__ __forceinline__ void x3_item(const DevSys &s, int m, int cg, T *red, T *xb, T *zb, T *yb) {
+  if constexpr (Geo<T, Q, L, LD>::CPW == 1) backward_item_x3<T, Q, L, LD, HOP>(s, m, cg, red, xb, zb, yb);
+}
+
 // ---------------------------------------------------------------------------- small FP64 kernels
 
 // Fixed-point iteration count.  The Jacobi map w -> (D^{-1} - 1)u - i D^{-1} (dt/2) H_c (u + w)
@@ -1785,14 +1887,18 @@ struct Kernels {
   void (*roll)(DevSys, double *, double *, int);
   void (*bwd)(DevSys, int);
   void (*bwd_xw)(DevSys, int);     // two wavefronts per item (one-column layouts only)
+  void (*bwd_x3)(DevSys, int);     // three wavefronts per item (one-column layouts only)
 };
 
 template <typename T, int Q, int L, int LD, bool HOP>
 Kernels make() {
-  void (*xw)(DevSys, int) = nullptr;
-  if constexpr (Geo<T, Q, L, LD>::CPW == 1) xw = k_backward_xw<T, Q, L, LD, HOP>;
+  void (*xw)(DevSys, int) = nullptr, (*x3)(DevSys, int) = nullptr;
+  if constexpr (Geo<T, Q, L, LD>::CPW == 1) {
+    xw = k_backward_xw<T, Q, L, LD, HOP>;
+    x3 = k_backward_x3<T, Q, L, LD, HOP>;
+  }
   return Kernels{k_forward<T, Q, L, LD, false, HOP>, k_forward<T, Q, L, LD, true, HOP>, k_backward<T, Q, L, LD, HOP>,
-                 xw};
+                 xw, x3};
 }
 
 // (q, L) -> lane digits, chosen so that each lane holds at most four entries
@@ -1884,6 +1990,27 @@ __global__ __launch_bounds__(128) void k_backward_xw_batch(const DevSys *sys, co
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(192) void k_backward_x3_batch(const DevSys *sys, const int4 *items) {
+  __shared__ __align__(16) T lds[x3_lds_elems<T, true>()];   // either variant
+  constexpr int XE = xchg_bytes<T, true>() / (int)sizeof(T);
+  T *xb = lds + (threadIdx.x >> 6) * XE;
+  T *zb = lds + 3 * XE;
+  T *yb = zb + 2 * 64 * 8;
+  T *red = yb + 2 * 64 * 8;
+  xchg_clear<T, true>(xb);
+  const int4 it = items[blockIdx.x];
+  const DevSys s = sys[it.x];
+  switch (it.w) {
+#define X(Q_, L_, LD_)                                                                             \
+    case SHAPE_##Q_##_##L_: x3_item<T, Q_, L_, LD_, false>(s, it.y, it.z, red, xb, zb, yb); break; \
+    case N_SHAPES + SHAPE_##Q_##_##L_: x3_item<T, Q_, L_, LD_, true>(s, it.y, it.z, red, xb, zb, yb); break;
+    QOC_SHAPES(X)
+#undef X
+    default: break;
+  }
+}
+
 int grid8(int n) { return (n + 7) / 8 * 8; }
 
 template <typename T, int K>
@@ -1910,12 +2037,16 @@ int phase_T(const DevSys &s, int phase, hipStream_t st, double *Wout, double *Uf
       small<T, SK_BPARTIAL>(s, st);
       small<T, SK_BFINAL>(s, st);
       break;
-    case PHASE_BACKWARD:
-      if (xw_backward(s) && K.bwd_xw)
+    case PHASE_BACKWARD: {
+      const int waves = bwd_waves(s);
+      if (waves == 3 && K.bwd_x3)
+        hipLaunchKernelGGL(K.bwd_x3, dim3(grid8(s.M * s.ncg_b)), dim3(192), 0, st, s, s.M * s.ncg_b);
+      else if (waves == 2 && K.bwd_xw)
         hipLaunchKernelGGL(K.bwd_xw, dim3(grid8(s.M * s.ncg_b)), dim3(128), 0, st, s, s.M * s.ncg_b);
       else
         hipLaunchKernelGGL(K.bwd, dim3(grid8(s.M * s.ncg_b)), dim3(64), 0, st, s, s.M * s.ncg_b);
       break;
+    }
     case PHASE_PROJECT:
       small<T, SK_SERIES>(s, st);
       small<T, SK_PROJECT>(s, st);
@@ -1952,20 +2083,31 @@ int batch_phase_T(const BatchPlan &p, int phase, hipStream_t st) {
       small_batched<T, SK_BPARTIAL>(p, st);
       small_batched<T, SK_BFINAL>(p, st);
       break;
-    case PHASE_BACKWARD:
-      if (p.n_xw > 0) {                   // the two-wavefront items run beside the others
-        hipError_t e = hipEventRecord(p.fork, st);
-        if (e == hipSuccess) e = hipStreamWaitEvent(p.aux, p.fork, 0);
-        if (e != hipSuccess) return (int)e;
+    case PHASE_BACKWARD: {
+      // the items of two and of three wavefronts run beside the others, each kind on a stream
+      // of the batch forked from st and joined back to it
+      hipError_t e = hipSuccess;
+      if (p.n_xw > 0 || p.n_x3 > 0) e = hipEventRecord(p.fork, st);
+      if (e == hipSuccess && p.n_xw > 0) e = hipStreamWaitEvent(p.aux, p.fork, 0);
+      if (e == hipSuccess && p.n_x3 > 0) e = hipStreamWaitEvent(p.aux2, p.fork, 0);
+      if (e != hipSuccess) return (int)e;
+      if (p.n_x3 > 0)
+        hipLaunchKernelGGL(k_backward_x3_batch<T>, dim3(p.n_x3), dim3(192), 0, p.aux2, p.sys, p.x3_items);
+      if (p.n_xw > 0)
         hipLaunchKernelGGL(k_backward_xw_batch<T>, dim3(p.n_xw), dim3(128), 0, p.aux, p.sys, p.xw_items);
-      }
       if (p.n_bwd > 0) hipLaunchKernelGGL(k_backward_batch<T>, dim3(p.n_bwd), dim3(64), 0, st, p.sys, p.bwd_items);
       if (p.n_xw > 0) {
-        hipError_t e = hipEventRecord(p.join, p.aux);
+        e = hipEventRecord(p.join, p.aux);
         if (e == hipSuccess) e = hipStreamWaitEvent(st, p.join, 0);
         if (e != hipSuccess) return (int)e;
       }
+      if (p.n_x3 > 0) {
+        e = hipEventRecord(p.join2, p.aux2);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, p.join2, 0);
+        if (e != hipSuccess) return (int)e;
+      }
       break;
+    }
     case PHASE_PROJECT:
       small_batched<T, SK_SERIES>(p, st);
       small_batched<T, SK_PROJECT>(p, st);

@@ -27,8 +27,9 @@ LIB_PATH = os.path.join(HERE, "libqoc.so")
 QOC_OK, QOC_EINVAL, QOC_ENOMEM, QOC_EDEVICE, QOC_ENOTCONV, QOC_EUNSUPPORTED, QOC_ESTATE = 0, -1, -2, -3, -4, -5, -6
 QOC_HOST, QOC_DEVICE = 0, 1
 QOC_FP64, QOC_FP32 = 0, 1
-QOC_BWD_AUTO, QOC_BWD_ONE_WAVE, QOC_BWD_TWO_WAVES = 0, 1, 2
-SCHEDULES = {"auto": QOC_BWD_AUTO, "one_wave": QOC_BWD_ONE_WAVE, "two_waves": QOC_BWD_TWO_WAVES}
+QOC_BWD_AUTO, QOC_BWD_ONE_WAVE, QOC_BWD_TWO_WAVES, QOC_BWD_THREE_WAVES = 0, 1, 2, 3
+SCHEDULES = {"auto": QOC_BWD_AUTO, "one_wave": QOC_BWD_ONE_WAVE, "two_waves": QOC_BWD_TWO_WAVES,
+             "three_waves": QOC_BWD_THREE_WAVES}
 
 EXPORTED = ["qoc_create", "qoc_destroy", "qoc_get_info", "qoc_set_stream", "qoc_set_controls",
             "qoc_set_window_states", "qoc_objective", "qoc_gradient", "qoc_rollout", "qoc_synchronize",
@@ -307,7 +308,7 @@ class System:
         _check(_lib.qoc_enable_timing(self.h, 1 if on else 0))
 
     def set_schedule(self, backward: str = "auto"):
-        """Backward-sweep schedule: "auto", "one_wave" or "two_waves" (qoc_set_schedule)."""
+        """Backward-sweep schedule: "auto", "one_wave", "two_waves" or "three_waves" (qoc_set_schedule)."""
         if backward not in SCHEDULES:
             raise ValueError(f"unknown backward schedule {backward!r}; expected one of {sorted(SCHEDULES)}")
         _check(_lib.qoc_set_schedule(self.h, SCHEDULES[backward]))
@@ -316,11 +317,12 @@ class System:
         """The backward schedule in force, with "auto" resolved."""
         v = ctypes.c_int32()
         _check(_lib.qoc_get_schedule(self.h, ctypes.byref(v)))
-        return {QOC_BWD_ONE_WAVE: "one_wave", QOC_BWD_TWO_WAVES: "two_waves"}[v.value]
+        return {QOC_BWD_ONE_WAVE: "one_wave", QOC_BWD_TWO_WAVES: "two_waves",
+                QOC_BWD_THREE_WAVES: "three_waves"}[v.value]
 
     def schedules(self):
         """The backward schedules this system's layout offers."""
-        return ["one_wave", "two_waves"] if self.info["columns_per_wave"] == 1 else ["one_wave"]
+        return ["one_wave", "two_waves", "three_waves"] if self.info["columns_per_wave"] == 1 else ["one_wave"]
 
     def timings(self):
         """Mean kernel ms per phase over the evaluations recorded since enable_timing()."""

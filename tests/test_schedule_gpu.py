@@ -4,7 +4,7 @@ Both schedules compute the discrete adjoint sweep of App. B; they differ only in
 state reconstruction and the adjoint are spread over wavefronts, so each must match the
 FP64 oracle to the stated tolerances on its own.  Forcing them also exercises the
 one-wavefront sweep of the one-column layout (4 qubits x 4 levels) at small window
-counts, where the default rule picks two wavefronts.  A schedule belongs to its
+counts, where the default rule picks three wavefronts.  A schedule belongs to its
 context: batched results equal the single calls under the same schedule bit for bit,
 also after the tuner has set them.
 """
@@ -30,7 +30,7 @@ def grad_rel(ga, gW, ga0, gW0):
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 @pytest.mark.parametrize("dip", [False, True])
-@pytest.mark.parametrize("sched", ["one_wave", "two_waves"])
+@pytest.mark.parametrize("sched", ["one_wave", "two_waves", "three_waves"])
 def test_forced_schedules_match_oracle(prec, dip, sched):
     w, alpha, W = TD.dipole_case(4, 4, 240, 6, seed=3) if dip else PG.small_case(4, 4, 240, 6, seed=3)
     P0, t0, ga0, gW0 = O.gradient(w, alpha, W)
@@ -41,7 +41,7 @@ def test_forced_schedules_match_oracle(prec, dip, sched):
     assert abs(P - P0) <= tol_P * abs(P0) and g <= tol_g
 
 
-@pytest.mark.parametrize("sched", ["one_wave", "two_waves"])
+@pytest.mark.parametrize("sched", ["one_wave", "two_waves", "three_waves"])
 def test_forced_schedules_with_checkpoints_and_one_step_windows(sched):
     """Checkpoint re-syncs inside windows, and windows of a single step."""
     for w, alpha, W in (PG.small_case(4, 4, 200, 4, ckpt=7), PG.small_case(4, 4, 8, 8)):
@@ -53,14 +53,16 @@ def test_forced_schedules_with_checkpoints_and_one_step_windows(sched):
 def test_schedule_query_and_errors():
     w, alpha, W = PG.small_case(4, 4, 64, 4)
     s = qoc.System(w, precision="fp32")
-    assert s.schedules() == ["one_wave", "two_waves"]
-    assert s.schedule() == "two_waves"                   # 4 x 16 items: the rule picks two wavefronts
+    assert s.schedules() == ["one_wave", "two_waves", "three_waves"]
+    assert s.schedule() == "three_waves"                 # 4 x 16 items: the rule picks three wavefronts
     s.set_schedule("one_wave")
     assert s.schedule() == "one_wave"
-    s.set_schedule("auto")
+    s.set_schedule("two_waves")
     assert s.schedule() == "two_waves"
+    s.set_schedule("auto")
+    assert s.schedule() == "three_waves"
     with pytest.raises(ValueError):
-        s.set_schedule("three_waves")
+        s.set_schedule("four_waves")
     lib = qoc.load_library()
     assert lib.qoc_set_schedule(s.h, 7) == qoc.QOC_EINVAL
     assert lib.qoc_get_schedule(s.h, None) == qoc.QOC_EINVAL
@@ -69,12 +71,17 @@ def test_schedule_query_and_errors():
     s = qoc.System(big, precision="fp32")
     assert s.schedule() == "one_wave"
     s.close()
+    for M, want in ((16, "three_waves"), (17, "one_wave")):  # FP64: at most 256 items
+        s = qoc.System(w.replace(n_windows=M, n_steps=10 * M), precision="fp64")
+        assert s.schedule() == want, (M, s.schedule())
+        s.close()
     w3, _, _ = PG.small_case(3, 4, 64, 4)                    # four columns per wavefront
     s = qoc.System(w3, precision="fp32")
     assert s.schedules() == ["one_wave"] and s.schedule() == "one_wave"
-    with pytest.raises(qoc.QocError) as e:
-        s.set_schedule("two_waves")
-    assert e.value.code == qoc.QOC_EUNSUPPORTED
+    for bad in ("two_waves", "three_waves"):
+        with pytest.raises(qoc.QocError) as e:
+            s.set_schedule(bad)
+        assert e.value.code == qoc.QOC_EUNSUPPORTED
     assert s.schedule() == "one_wave"
     s.close()
 
@@ -100,7 +107,7 @@ def _members(seed=0):
     out = []
     for i, (q, L, n, M, sched) in enumerate([(4, 4, 160, 4, "one_wave"), (4, 4, 160, 4, "two_waves"),
                                                (4, 4, 96, 8, "auto"), (3, 4, 150, 5, "auto"),
-                                               (2, 3, 200, 3, "auto")]):
+                                               (2, 3, 200, 3, "auto"), (4, 4, 130, 5, "three_waves")]):
         w, alpha, W = PG.small_case(q, L, n, M, seed=seed + i)
         out.append((w, alpha, W, sched))
     return out
@@ -126,7 +133,8 @@ def _check_equal_to_solo(members, systems):
 def test_batch_with_forced_schedules_equals_solo():
     members = _members()
     systems = _open(members)
-    assert [s.schedule() for s in systems][:3] == ["one_wave", "two_waves", "two_waves"]
+    assert [s.schedule() for s in systems] == ["one_wave", "two_waves", "three_waves", "one_wave", "one_wave",
+                                               "three_waves"]
     b = qoc.Batch(max_contexts=8, max_items=4096)
     b.run(systems)
     torch.cuda.synchronize()
@@ -140,8 +148,8 @@ def test_tuner_choices_are_valid_and_keep_bit_identity():
     members = _members(seed=10)
     systems = _open(members)
     r = autotune.tune_system(systems[0], reps=2, warmup=1)
-    assert r["choice"] in ("one_wave", "two_waves") and systems[0].schedule() == r["choice"]
-    assert all(ms > 0 for ms in r["backward_ms"].values()) and len(r["backward_ms"]) == 2
+    assert r["choice"] in ("one_wave", "two_waves", "three_waves") and systems[0].schedule() == r["choice"]
+    assert all(ms > 0 for ms in r["backward_ms"].values()) and len(r["backward_ms"]) == 3
     r3 = autotune.tune_system(systems[3], reps=1, warmup=1)          # only one schedule offered
     assert r3["choice"] == "one_wave" and list(r3["backward_ms"]) == ["one_wave"]
     b = qoc.Batch(max_contexts=8, max_items=4096)
@@ -152,7 +160,7 @@ def test_tuner_choices_are_valid_and_keep_bit_identity():
         g = autotune.group_key(s)
         if g in rb["choice"]:
             assert s.schedule() == rb["choice"][g]
-    assert rb["tuned_ms"] <= rb["auto_ms"] and len(rb["trials"]) == 1 + len(keys)
+    assert rb["tuned_ms"] <= rb["auto_ms"] and len(rb["trials"]) >= 1 + 2 * len(keys)
     b.run(systems)
     torch.cuda.synchronize()
     _check_equal_to_solo(members, systems)
