@@ -328,7 +328,8 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-plain-requests", type=int, default=600)
-    ap.add_argument("--serve-load", type=float, default=0.7, help="arrival rate as a fraction of the batched mix rate")
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="arrival rate as a fraction of the batched mix rate under the default schedule rule")
     ap.add_argument("--hbm-budget-gb", type=float, default=6.0)
     ap.add_argument("--opt-runs", default="2:16:3000,2:1:500,3:32:6000,3:1:400",
                     help="optimisation runs on the paper's QFT systems, qubits:windows:iteration-cap, "
@@ -471,7 +472,8 @@ def main():
         try:
             result["batched_mix"] = bench_batch(args.seed, args.batch_reps, log)
             if "serve" in extras:
-                rate = args.serve_load * result["batched_mix"]["evals_per_s"]
+                # the server runs the default schedule rule: load it relative to the mix's rate under that rule
+                rate = args.serve_load * 64e3 / result["batched_mix"]["schedule"]["default_rule_ms"]
                 result["serving"] = bench_serve(rate, args.serve_requests, args.serve_plain_requests, args.seed,
                                                 args.hbm_budget_gb, log)
         except Exception as e:   # the headline line must still be printed
