@@ -127,23 +127,29 @@ int qoc_set_stream(qoc_ctx *ctx, void *hip_stream);
 /* Schedule of the backward (adjoint) sweep, App. B: a choice of how the work is
  * spread over wavefronts, not of what is computed.  Two schedules give the same
  * result up to the rounding order of the per-step inner products.
- *   QOC_BWD_AUTO        the library's rule (the default): three wavefronts where
- *                       the layout allows it and the sweep has at most 1024 (FP32)
- *                       or 256 (FP64) (window, column group) items, else one;
+ *   QOC_BWD_AUTO        the library's rule (the default): the layout's multi-
+ *                       wavefront schedule (THREE_WAVES for layouts with one column
+ *                       per wavefront, TWO_WAVES for the others) when the sweep has
+ *                       at most 1024 (FP32) or 256 (FP64) (window, column group)
+ *                       items, else ONE_WAVE;
  *   QOC_BWD_ONE_WAVE    one wavefront per item reconstructs the state and
  *                       propagates the adjoint (in the two halves of the wavefront
- *                       for layouts with two or more columns per wavefront);
- *   QOC_BWD_TWO_WAVES   the state and the adjoint in two wavefronts of one block,
- *                       handing the state over through LDS each step;
- *   QOC_BWD_THREE_WAVES as TWO_WAVES, plus a third wavefront that takes the
- *                       per-step inner products from both solutions, one step
- *                       behind, so that a step costs the solving wavefronts one
- *                       solve (for long windows on an otherwise idle GPU).
- * TWO_WAVES and THREE_WAVES need a layout with one column per wavefront, else
- * QOC_EUNSUPPORTED.  The setting belongs to the context and is used by its single
- * and batched calls alike, so a batched result still equals the single call's bit
- * for bit.  qoc_get_schedule writes the schedule in force with AUTO resolved
- * (ONE_WAVE, TWO_WAVES or THREE_WAVES).  Errors: QOC_EINVAL (NULL context or
+ *                       for layouts with two or more columns per wavefront) and
+ *                       takes the per-step inner products;
+ *   QOC_BWD_TWO_WAVES   two wavefronts per item.  One column per wavefront: the
+ *                       state and the adjoint in one wavefront each, the state
+ *                       handed over through LDS each step.  Two or more: the solves
+ *                       of both halves in one wavefront, the inner products in the
+ *                       other, one step behind, from LDS records;
+ *   QOC_BWD_THREE_WAVES (one column per wavefront only, else QOC_EUNSUPPORTED)
+ *                       state, adjoint and inner products in one wavefront each,
+ *                       the inner products one step behind, so that a step costs
+ *                       the solving wavefronts one solve.
+ * More wavefronts shorten a window's chain of steps (long windows on an otherwise
+ * idle GPU); one spends the fewest instructions per item-step.  The setting belongs
+ * to the context and is used by its single and batched calls alike, so a batched
+ * result still equals the single call's bit for bit.  qoc_get_schedule writes the
+ * schedule in force with AUTO resolved.  Errors: QOC_EINVAL (NULL context or
  * output, unknown value). */
 #define QOC_BWD_AUTO 0
 #define QOC_BWD_ONE_WAVE 1

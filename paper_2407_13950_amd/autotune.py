@@ -15,8 +15,8 @@ of the launch; the functions here measure instead.
   so the candidates are timed on the batch itself.  Tunable systems are grouped
   by (qubits, levels, windows, steps, dipole, precision).  The makespan is a
   maximum over the members' chains, so moving one group alone often changes
-  nothing; the tuner first tries every schedule for all groups at once against
-  the default rule, keeps the best, and then switches each group in turn to every
+  nothing; the tuner first tries every schedule for all groups that offer it at
+  once against the default rule, keeps the best, and then switches each group in turn to every
   other schedule while the rest stay as they are (one pass of coordinate descent).
   A move is kept when it shortens the batch by more than `min_gain`.
 
@@ -90,13 +90,13 @@ def tune_batch(batch, systems: Sequence, reps: int = 3, want_grad: Optional[Sequ
     auto_ms = best_ms
     trials = [{"assignment": dict(current), "ms": best_ms}]
     offered = sorted({c for members in groups.values() for c in members[0].schedules()})
-    for cand in offered:                                          # joint moves: every group at once
-        assign = {g: cand for g in groups}
+    for cand in offered:                    # joint moves: every group that offers the schedule at once
+        assign = {g: (cand if cand in members[0].schedules() else current[g]) for g, members in groups.items()}
         if assign == current:
             continue
         for g, members in groups.items():
             for s in members:
-                s.set_schedule(cand)
+                s.set_schedule(assign[g])
         ms = _time_batch(batch, systems, reps, want_grad)
         trials.append({"assignment": dict(assign), "ms": ms})
         if ms < best_ms * (1.0 - min_gain):

@@ -330,8 +330,8 @@ int qoc_set_schedule(qoc_ctx *ctx, int32_t backward) {
   if (backward != QOC_BWD_AUTO && backward != QOC_BWD_ONE_WAVE && backward != QOC_BWD_TWO_WAVES &&
       backward != QOC_BWD_THREE_WAVES)
     return fail(QOC_EINVAL, "qoc_set_schedule: unknown backward schedule " + std::to_string(backward));
-  if ((backward == QOC_BWD_TWO_WAVES || backward == QOC_BWD_THREE_WAVES) && ctx->dev.cpw != 1)
-    return fail(QOC_EUNSUPPORTED, "qoc_set_schedule: a backward of two or three wavefronts needs a "
+  if (backward == QOC_BWD_THREE_WAVES && ctx->dev.cpw != 1)
+    return fail(QOC_EUNSUPPORTED, "qoc_set_schedule: a backward of three wavefronts needs a "
                                   "one-column-per-wavefront layout");
   ctx->dev.bwd_sched = backward;
   return QOC_OK;

@@ -80,25 +80,27 @@ int launch_phase(const DevSys &s, int phase, hipStream_t st, double *Wout = null
 // Several systems evaluated together: the propagation phases run as one launch
 // over all (system, window, column group) items, each small kernel as one launch
 // over a (system, block) table.  All systems share the precision `fp64`.
-// Wavefronts per backward item (1, 2 or 3; more than one only for layouts with one
-// column per wavefront): the caller's schedule, or by default three (state, adjoint,
-// inner products) when the launch would otherwise leave SIMDs idle -- at most 1024
-// items (one wavefront per SIMD) in FP32, 256 in FP64, whose solving wavefronts need
-// more registers -- and one otherwise.  Two wavefronts (state and adjoint, the inner
+// Wavefronts per backward item: the caller's schedule or, by default, several when the
+// launch would otherwise leave SIMDs idle -- at most 1024 items (one wavefront per SIMD)
+// in FP32, 256 in FP64, whose solving wavefronts need more registers -- and one
+// otherwise.  "Several" is three for layouts with one column per wavefront (state,
+// adjoint, inner products) and two for the others (the solves of both halves, and the
+// inner products).  Two wavefronts on a one-column layout (state and adjoint, the inner
 // products on the adjoint's chain) only on request.  A function of the system and its
 // schedule setting alone, so a batched evaluation makes the same choice as a solo one.
-#ifndef QOC_X3_MAX_ITEMS_FP32
-#define QOC_X3_MAX_ITEMS_FP32 1024
+#ifndef QOC_MULTI_WAVE_MAX_ITEMS_FP32
+#define QOC_MULTI_WAVE_MAX_ITEMS_FP32 1024
 #endif
-#ifndef QOC_X3_MAX_ITEMS_FP64
-#define QOC_X3_MAX_ITEMS_FP64 256
+#ifndef QOC_MULTI_WAVE_MAX_ITEMS_FP64
+#define QOC_MULTI_WAVE_MAX_ITEMS_FP64 256
 #endif
 inline int bwd_waves(const DevSys &s) {
-  if (s.cpw != 1 || s.bwd_sched == QOC_BWD_ONE_WAVE) return 1;
+  if (s.bwd_sched == QOC_BWD_ONE_WAVE) return 1;
   if (s.bwd_sched == QOC_BWD_TWO_WAVES) return 2;
-  if (s.bwd_sched == QOC_BWD_THREE_WAVES) return 3;
+  if (s.bwd_sched == QOC_BWD_THREE_WAVES) return s.cpw == 1 ? 3 : 1;
   const long long items = (long long)s.M * s.ncg_b;
-  return items <= (s.fp64 ? QOC_X3_MAX_ITEMS_FP64 : QOC_X3_MAX_ITEMS_FP32) ? 3 : 1;
+  if (items > (s.fp64 ? QOC_MULTI_WAVE_MAX_ITEMS_FP64 : QOC_MULTI_WAVE_MAX_ITEMS_FP32)) return 1;
+  return s.cpw == 1 ? 3 : 2;
 }
 
 struct BatchPlan {

@@ -1509,10 +1509,105 @@ __device__ __forceinline__ void backward_item_xw(const DevSys &s, int m, int cg,
   for (int e = 0; e < G::EPL; ++e) l0[ln.row(e)] = double2{ar[e], ai[e]};
 }
 
+// Layouts with two or more columns per wavefront, two wavefronts per item: wavefront 0
+// solves the state (lanes 0..31) and the adjoint (lanes 32..63) as the split sweep does and
+// leaves each lane's step solution in a double-buffered LDS record; in the next iteration
+// wavefront 1 reads z (the state lane's record) and y (the adjoint lane's, 32 lanes on) and
+// takes that step's inner products and the series flush, so they leave the solving
+// wavefront's chain.  Loop and record reuse as in backward_item_x3: one iteration more
+// than the window has steps, each ending with the block barrier outside the role branches.
+template <typename T, int Q, int L, int LD, bool HOP>
+__device__ __forceinline__ void backward_item_sx(const DevSys &s, int m, int cg, T *red, T *xb, T *rb) {
+  using G = Geo<T, Q, L, LD>;
+  constexpr int RS = 64 * 2 * G::EPL;               // elements of one step's record
+  static_assert(2 * G::EPL <= 8, "a step record exceeds its LDS slot (64 lanes x 8 elements)");
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // 0: solves, 1: inner products
+  const int item = m * s.ncg_b + cg;
+  Lane<T, Q, L, LD> ln;
+  ln.init(s, cg, xb, true);
+  if constexpr (HOP) {
+    if (wv == 0) ln.init_hop(s);
+  }
+  const bool adj = ln.lane >= 32;                   // state (false) or adjoint (true) half
+  const long long k0 = s.kstart[m], k1 = s.kstart[m + 1];
+  double ar[G::EPL], ai[G::EPL];                    // U (state lanes) or Lambda (adjoint lanes), FP64
+  if (wv == 0) backward_start<T, Q, L, LD>(s, m, ln, adj, ar, ai);
+  const int kit = kit_of(s);
+  const T *ctrl = reinterpret_cast<const T *>(s.ctrl);
+  double *ser = s.series + (size_t)item * s.maxlen * 2 * Q;
+  CkptPos cp(s, k0, k1);
+  typename C2<T>::type cnext[Q];
+  if (wv == 0) load_ctrl<T, Q>(ctrl, k1 - 1, cnext);
+  for (long long k = k1 - 1; k >= k0 - 1; --k) {
+    if (wv == 0 && k >= k0) {                       // solve step k, leave z or y in record k & 1
+      typename C2<T>::type ccur[Q];
+#pragma unroll
+      for (int j = 0; j < Q; ++j) ccur[j] = cnext[j];
+      load_ctrl<T, Q>(ctrl, k > k0 ? k - 1 : k, cnext);
+      Coef<T, Q, L, LD> cf;
+      step_coeffs<T, Q, L, LD>(ln, ccur, cf);
+      T ur[G::EPL], ui[G::EPL], wr[G::EPL], wi[G::EPL];
+#pragma unroll
+      for (int e = 0; e < G::EPL; ++e) {
+        ur[e] = (T)ar[e];
+        ui[e] = (T)ai[e];
+      }
+      solve_increment<T, Q, L, LD, true, HOP>(ln, kit, cf, ur, ui, wr, wi);
+      T *rec = rb + (size_t)(k & 1) * RS + ln.lane * 2 * G::EPL;
+#pragma unroll
+      for (int e = 0; e < G::EPL; ++e) {
+        rec[2 * e] = ur[e] + wr[e];
+        rec[2 * e + 1] = ui[e] + wi[e];
+        ar[e] += 2.0 * (double)wr[e];
+        ai[e] += 2.0 * (double)wi[e];
+      }
+      ckpt_step<T, Q, L, LD>(s, m, ln, !adj, cp, ar, ai);
+    }
+    if (wv == 1 && k < k1 - 1) {                    // inner products of step k + 1
+      const long long kp = k + 1;
+      const T *base = rb + (size_t)(kp & 1) * RS;
+      const T *zrec = base + (ln.lane & 31) * 2 * G::EPL;
+      const T *yrec = base + ((ln.lane & 31) + 32) * 2 * G::EPL;
+      T zr[G::EPL], zi[G::EPL], yr[G::EPL], yi[G::EPL];
+#pragma unroll
+      for (int e = 0; e < G::EPL; ++e) {
+        zr[e] = zrec[2 * e];
+        zi[e] = zrec[2 * e + 1];
+        yr[e] = yrec[2 * e];
+        yi[e] = yrec[2 * e + 1];
+      }
+      T s1[Q], s2[Q];
+      inner_register_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
+      inner_lane_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {                 // lanes 32..63 repeat lanes 0..31: count them once
+        s1[j] = adj ? (T)0 : s1[j];
+        s2[j] = adj ? (T)0 : s2[j];
+      }
+      series_put<T, Q>(red, ser, ln.lane, (int)(kp - k0), (int)(k1 - k0), s1, s2);
+    }
+    __syncthreads();                                // every wavefront, every iteration
+  }
+  if (wv != 0 || !ln.valid || !adj) return;
+  double2 *l0 = reinterpret_cast<double2 *>(s.lam0) + ((size_t)m * s.E + ln.col) * s.N;
+#pragma unroll
+  for (int e = 0; e < G::EPL; ++e) l0[ln.row(e)] = double2{ar[e], ai[e]};
+}
+
 // Per block: wavefront 0's and wavefront 1's exchange buffers, the double-buffered z
 // record, and wavefront 1's series buffer.
 template <typename T, bool HOP>
 constexpr int xw_lds_elems() { return 2 * (xchg_bytes<T, HOP>() / (int)sizeof(T)) + 2 * 64 * 8 + red_elems<T>(); }
+
+// Two wavefronts per item: state and adjoint for one-column layouts, solves and inner
+// products for layouts with two or more columns per wavefront.
+template <typename T, int Q, int L, int LD, bool HOP>
+__device__ __forceinline__ void xw_item(const DevSys &s, int m, int cg, T *red, T *xb, T *zb) {
+  if constexpr (Geo<T, Q, L, LD>::CPW == 1)
+    backward_item_xw<T, Q, L, LD, HOP>(s, m, cg, red, xb, zb);
+  else
+    backward_item_sx<T, Q, L, LD, HOP>(s, m, cg, red, xb, zb);
+}
 
 template <typename T, int Q, int L, int LD, bool HOP>
 __global__ __launch_bounds__(128) void k_backward_xw(DevSys s, int nitems) {
@@ -1524,12 +1619,7 @@ __global__ __launch_bounds__(128) void k_backward_xw(DevSys s, int nitems) {
   T *zb = lds + 2 * XE;
   T *red = zb + 2 * 64 * 8;
   xchg_clear<T, HOP>(xb);
-  backward_item_xw<T, Q, L, LD, HOP>(s, item / s.ncg_b, item % s.ncg_b, red, xb, zb);
-}
-
-template <typename T, int Q, int L, int LD, bool HOP>
-__device__ __forceinline__ void xw_item(const DevSys &s, int m, int cg, T *red, T *xb, T *zb) {
-  if constexpr (Geo<T, Q, L, LD>::CPW == 1) backward_item_xw<T, Q, L, LD, HOP>(s, m, cg, red, xb, zb);
+  xw_item<T, Q, L, LD, HOP>(s, item / s.ncg_b, item % s.ncg_b, red, xb, zb);
 }
 
 // Three wavefronts per (window, column group) for the one-column-per-wavefront layout,
@@ -1546,6 +1636,7 @@ template <typename T, int Q, int L, int LD, bool HOP>
 __device__ __forceinline__ void backward_item_x3(const DevSys &s, int m, int cg, T *red, T *xb, T *zb, T *yb) {
   using G = Geo<T, Q, L, LD>;
   constexpr int RS = 64 * 2 * G::EPL;               // elements of one step's record
+  static_assert(2 * G::EPL <= 8, "a step record exceeds its LDS slot (64 lanes x 8 elements)");
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // 0: state, 1: adjoint, 2: inner products
   const int item = m * s.ncg_b + cg;
   Lane<T, Q, L, LD> ln;
@@ -1886,17 +1977,14 @@ struct Kernels {
   void (*fwd)(DevSys, double *, double *, int);
   void (*roll)(DevSys, double *, double *, int);
   void (*bwd)(DevSys, int);
-  void (*bwd_xw)(DevSys, int);     // two wavefronts per item (one-column layouts only)
+  void (*bwd_xw)(DevSys, int);     // two wavefronts per item
   void (*bwd_x3)(DevSys, int);     // three wavefronts per item (one-column layouts only)
 };
 
 template <typename T, int Q, int L, int LD, bool HOP>
 Kernels make() {
-  void (*xw)(DevSys, int) = nullptr, (*x3)(DevSys, int) = nullptr;
-  if constexpr (Geo<T, Q, L, LD>::CPW == 1) {
-    xw = k_backward_xw<T, Q, L, LD, HOP>;
-    x3 = k_backward_x3<T, Q, L, LD, HOP>;
-  }
+  void (*xw)(DevSys, int) = k_backward_xw<T, Q, L, LD, HOP>, (*x3)(DevSys, int) = nullptr;
+  if constexpr (Geo<T, Q, L, LD>::CPW == 1) x3 = k_backward_x3<T, Q, L, LD, HOP>;
   return Kernels{k_forward<T, Q, L, LD, false, HOP>, k_forward<T, Q, L, LD, true, HOP>, k_backward<T, Q, L, LD, HOP>,
                  xw, x3};
 }

@@ -322,7 +322,7 @@ class System:
 
     def schedules(self):
         """The backward schedules this system's layout offers."""
-        return ["one_wave", "two_waves", "three_waves"] if self.info["columns_per_wave"] == 1 else ["one_wave"]
+        return ["one_wave", "two_waves", "three_waves"] if self.info["columns_per_wave"] == 1 else ["one_wave", "two_waves"]
 
     def timings(self):
         """Mean kernel ms per phase over the evaluations recorded since enable_timing()."""
