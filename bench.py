@@ -113,6 +113,8 @@ def bench_batch(seed, reps, log):
     torch.cuda.synchronize()
     # backward schedules of the one-column systems measured on this batch (untimed)
     tuned = autotune.tune_batch(b, systems, reps=3)
+    one = [t["ms"] for t in tuned["trials"] if set(t["assignment"].values()) <= {"one_wave"}]
+    one_wave_ms = one[0] if one else tuned["auto_ms"]
     log("batch schedule: " + ", ".join(f"{g}: {c}" for g, c in tuned["choice"].items())
         + f" ({tuned['auto_ms']:.1f} ms by the default rule -> {tuned['tuned_ms']:.1f} ms)")
     t0 = time.perf_counter()
@@ -137,7 +139,7 @@ def bench_batch(seed, reps, log):
            "batch": "32x(q2,L3,N_T=4000) + 24x(q3,L4,N_T=20000) + 8x(q4,L4,N_T=100000), M in {4,16,64,128}",
            "reps": reps, "equal_to_solo_bitwise": bool(same),
            "schedule": {"choice": tuned["choice"], "default_rule_ms": tuned["auto_ms"],
-                        "tuned_ms": tuned["tuned_ms"], "trials": tuned["trials"]}}
+                        "tuned_ms": tuned["tuned_ms"], "one_wave_ms": one_wave_ms, "trials": tuned["trials"]}}
     log(f"batched mix: {out['evals_per_s']:.1f} evals/s, {out['ms_per_batch']:.1f} ms per 64-eval batch")
     for s in systems:
         s.close()
@@ -472,7 +474,8 @@ def main():
         try:
             result["batched_mix"] = bench_batch(args.seed, args.batch_reps, log)
             if "serve" in extras:
-                # the server runs the default schedule rule: load it relative to the mix's rate under that rule
+                # the server runs the library's default schedule rule: load it relative to the mix's
+                # rate under that rule
                 rate = args.serve_load * 64e3 / result["batched_mix"]["schedule"]["default_rule_ms"]
                 result["serving"] = bench_serve(rate, args.serve_requests, args.serve_plain_requests, args.seed,
                                                 args.hbm_budget_gb, log)

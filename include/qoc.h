@@ -210,10 +210,10 @@ int qoc_rollout(qoc_ctx *ctx, double *W_out, double *U_out, int32_t where);
  * QOC_EINVAL (mixed precision/device, duplicates, more contexts or items than
  * the batch was created for), QOC_ESTATE (a context without controls/states).
  * Results agree with the single-context calls bit for bit (same kernels, same
- * reduction order).  Backward sweeps of two and of three wavefronts per item
- * (qoc_set_schedule) run on two streams the batch owns, forked from hip_stream and
- * joined back to it within the call's work, so the caller sees ordinary stream
- * order.  max_items bounds the forward items and, separately, the
+ * reduction order).  When a call's backward items are of more than one schedule
+ * (qoc_set_schedule), those of two and of three wavefronts run on two streams the
+ * batch owns, forked from hip_stream and joined back to it within the call's work,
+ * so the caller sees ordinary stream order.  max_items bounds the forward items and, separately, the
  * backward items (window x backward column group) of one call. */
 typedef struct qoc_batch qoc_batch;
 int qoc_batch_create(int32_t device, int32_t max_contexts, int64_t max_items, qoc_batch **out);

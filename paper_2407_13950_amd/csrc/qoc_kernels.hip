@@ -2172,8 +2172,16 @@ int batch_phase_T(const BatchPlan &p, int phase, hipStream_t st) {
       small_batched<T, SK_BFINAL>(p, st);
       break;
     case PHASE_BACKWARD: {
-      // the items of two and of three wavefronts run beside the others, each kind on a stream
-      // of the batch forked from st and joined back to it
+      // a single kind of backward items runs on st; with several kinds, the items of two and
+      // of three wavefronts run beside the others, each kind on a stream of the batch forked
+      // from st and joined back to it
+      const int kinds = (p.n_bwd > 0) + (p.n_xw > 0) + (p.n_x3 > 0);
+      if (kinds <= 1) {
+        if (p.n_x3 > 0) hipLaunchKernelGGL(k_backward_x3_batch<T>, dim3(p.n_x3), dim3(192), 0, st, p.sys, p.x3_items);
+        if (p.n_xw > 0) hipLaunchKernelGGL(k_backward_xw_batch<T>, dim3(p.n_xw), dim3(128), 0, st, p.sys, p.xw_items);
+        if (p.n_bwd > 0) hipLaunchKernelGGL(k_backward_batch<T>, dim3(p.n_bwd), dim3(64), 0, st, p.sys, p.bwd_items);
+        break;
+      }
       hipError_t e = hipSuccess;
       if (p.n_xw > 0 || p.n_x3 > 0) e = hipEventRecord(p.fork, st);
       if (e == hipSuccess && p.n_xw > 0) e = hipStreamWaitEvent(p.aux, p.fork, 0);

@@ -223,12 +223,16 @@ class QocBackend(Backend):
     """Runs batches through the C ABI: one qoc_batch per stream, one qoc context per run."""
 
     def __init__(self, precision: str = "fp32", n_streams: int = 4, max_batch: int = 64, max_items: int = 400000,
-                 keep_results: bool = False, schedules: Optional[Dict[str, str]] = None):
+                 keep_results: bool = False, schedule: str = "auto",
+                 schedules: Optional[Dict[str, str]] = None):
+        """schedule: backward schedule of every context (qoc_set_schedule; default: the library's
+        rule); schedules: overrides per system group (autotune.group_key)."""
         import torch
         from . import autotune, qoc
         self.torch, self.qoc, self.autotune = torch, qoc, autotune
         self.precision = precision
-        self.schedules = schedules or {}        # backward schedule per system group (autotune.group_key)
+        self.schedule = schedule
+        self.schedules = schedules or {}
         self._streams = [torch.cuda.Stream() for _ in range(n_streams)]   # default priority
         self._batches = [qoc.Batch(max_batch, max_items) for _ in range(n_streams)]
         self.keep_results = keep_results
@@ -254,7 +258,7 @@ class QocBackend(Backend):
     def open(self, w, initial):
         torch = self.torch
         alpha0, W0 = initial
-        s = self.qoc.System(w, precision=self.precision)
+        s = self.qoc.System(w, precision=self.precision, backward_schedule=self.schedule)
         self.autotune.apply([s], self.schedules)
         h = {"system": s, "w": w, "alpha": torch.as_tensor(alpha0, device="cuda").clone(),
              "W": None, "g_alpha": None, "g_W": None}

@@ -18,10 +18,13 @@ def small_runs(n_runs, seed=0):
     return runs
 
 
-def test_served_results_equal_solo_results():
+@pytest.mark.parametrize("schedule", ["one_wave", "auto"])
+def test_served_results_equal_solo_results(schedule):
+    """Every served result equals the single call with the same backward schedule, bit for bit."""
     runs = small_runs(9)
     _, reqs, counts = serve.make_trace(120, rate=3000.0, seed=1, n_runs=9)
-    be = serve.QocBackend(precision="fp32", n_streams=2, max_batch=16, max_items=100000, keep_results=True)
+    be = serve.QocBackend(precision="fp32", n_streams=2, max_batch=16, max_items=100000, keep_results=True,
+                          schedule=schedule)
     srv = serve.Server(be, hbm_budget=8 << 30, max_batch=16)
     for r, w in runs.items():
         srv.register_run(r, w, counts[r], initial=serve.initial_inputs(w, 100 + r))
@@ -34,7 +37,7 @@ def test_served_results_equal_solo_results():
     for q in srv.completed:
         w = runs[q.run_id]
         if q.run_id not in solo:
-            solo[q.run_id] = qoc.System(w, precision="fp32")
+            solo[q.run_id] = qoc.System(w, precision="fp32", backward_schedule=schedule)
         s = solo[q.run_id]
         alpha, W = q.inputs
         s.set_controls(alpha)
