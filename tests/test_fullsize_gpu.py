@@ -29,8 +29,8 @@ def flat(ga, gW):
     return np.concatenate([ga, np.asarray(gW).view(np.float64).ravel()])
 
 
-def gpu_gradient(w, alpha, W, precision):
-    s = qoc.System(w, precision=precision)
+def gpu_gradient(w, alpha, W, precision, schedule="auto"):
+    s = qoc.System(w, precision=precision, backward_schedule=schedule)
     s.set_controls(torch.tensor(alpha, device="cuda"))
     s.set_window_states(torch.tensor(W, device="cuda"))
     P, terms, ga, gW = s.gradient(device=True)
@@ -60,9 +60,9 @@ def test_small_configs_full_size(mk):
     t0 = time.time()
     P0, t0_, ga0, gW0 = O.gradient(w, alpha, W)
     print(f"{w.name}: oracle gradient {time.time() - t0:.1f} s", flush=True)
-    for prec in ("fp64", "fp32"):
-        P, terms, ga, gW = gpu_gradient(w, alpha, W, prec)
-        e = report(w.name, prec, P, P0, ga, ga0, gW, gW0)
+    for prec, sched in (("fp64", "auto"), ("fp32", "auto"), ("fp64", "one_wave"), ("fp32", "one_wave")):
+        P, terms, ga, gW = gpu_gradient(w, alpha, W, prec, sched)
+        e = report(f"{w.name} {sched}", prec, P, P0, ga, ga0, gW, gW0)
         if prec == "fp64":
             assert e["P"] <= 1e-11 and e["grad"] <= 1e-10
             assert np.allclose(terms, t0_, rtol=1e-10, atol=1e-14)
@@ -85,11 +85,14 @@ def c3_problem():
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_c3_full_size_matches_oracle(c3_problem, prec):
+@pytest.mark.parametrize("prec,sched", [("fp64", "auto"), ("fp32", "auto"), ("fp32", "two_waves"),
+                                        ("fp32", "three_waves")])
+def test_c3_full_size_matches_oracle(c3_problem, prec, sched):
+    """The bench's configuration (128 windows) under the default schedule and under the
+    multi-wavefront ones a tuned batch may pick."""
     w, alpha, W, (P0, t0, ga0, gW0) = c3_problem
-    P, terms, ga, gW = gpu_gradient(w, alpha, W, prec)
-    e = report(w.name, prec, P, P0, ga, ga0, gW, gW0)
+    P, terms, ga, gW = gpu_gradient(w, alpha, W, prec, sched)
+    e = report(f"{w.name} {sched}", prec, P, P0, ga, ga0, gW, gW0)
     pen_rel = np.max(np.abs(terms[4:] - t0[4:]) / np.abs(t0[4:]))
     print(f"  per-window penalty max rel err {pen_rel:.2e}", flush=True)
     if prec == "fp64":

@@ -47,9 +47,11 @@ SPLIT_SHAPES = [(1, 3, 100, 3), (2, 3, 403, 5), (2, 4, 210, 4), (3, 2, 150, 5), 
 
 @pytest.mark.parametrize("q,L,n_steps,M", SPLIT_SHAPES)
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_two_waves_on_multi_column_layouts_match_oracle(q, L, n_steps, M, prec):
-    """Layouts with several columns per wavefront: the solves in one wavefront, the inner products in
-    a second one step behind; with and without the dipole chain."""
+@pytest.mark.parametrize("sched", ["one_wave", "two_waves"])
+def test_schedules_on_multi_column_layouts_match_oracle(q, L, n_steps, M, prec, sched):
+    """Layouts with several columns per wavefront, with and without the dipole chain: one wavefront
+    (state and adjoint in its two halves, inner products on its chain), or two (the solves in one,
+    the inner products in a second, one step behind)."""
     cases = [PG.small_case(q, L, n_steps, M, seed=4)]
     if q >= 2:
         cases.append(TD.dipole_case(q, L, n_steps, M, seed=4))
@@ -58,9 +60,9 @@ def test_two_waves_on_multi_column_layouts_match_oracle(q, L, n_steps, M, prec):
         s = qoc.System(w, precision=prec)
         assert s.info["columns_per_wave"] >= 2 and s.schedules() == ["one_wave", "two_waves"]
         s.close()
-        P, t, ga, gW = PG.run_gpu(w, alpha, W, prec, backward_schedule="two_waves")
+        P, t, ga, gW = PG.run_gpu(w, alpha, W, prec, backward_schedule=sched)
         g = grad_rel(ga, gW, ga0, gW0) if M > 1 else PG.rel(ga, ga0)
-        print(f"{w.name} {prec} two_waves: P rel {abs(P - P0) / abs(P0):.2e}  grad rel-L2 {g:.2e}", flush=True)
+        print(f"{w.name} {prec} {sched}: P rel {abs(P - P0) / abs(P0):.2e}  grad rel-L2 {g:.2e}", flush=True)
         tol_P, tol_g = TOL[prec]
         assert abs(P - P0) <= tol_P * abs(P0) and g <= tol_g
 
@@ -136,7 +138,8 @@ def _members(seed=0):
     for i, (q, L, n, M, sched) in enumerate([(4, 4, 160, 4, "one_wave"), (4, 4, 160, 4, "two_waves"),
                                                (4, 4, 96, 8, "auto"), (3, 4, 150, 5, "auto"),
                                                (2, 3, 200, 3, "auto"), (4, 4, 130, 5, "three_waves"),
-                                               (3, 4, 120, 4, "two_waves"), (2, 2, 90, 3, "two_waves")]):
+                                               (3, 4, 120, 4, "two_waves"), (2, 2, 90, 3, "two_waves"),
+                                               (2, 4, 100, 3, "one_wave")]):
         w, alpha, W = PG.small_case(q, L, n, M, seed=seed + i)
         out.append((w, alpha, W, sched))
     return out
@@ -163,8 +166,8 @@ def test_batch_with_forced_schedules_equals_solo():
     members = _members()
     systems = _open(members)
     assert [s.schedule() for s in systems] == ["one_wave", "two_waves", "three_waves", "two_waves", "two_waves",
-                                               "three_waves", "two_waves", "two_waves"]
-    b = qoc.Batch(max_contexts=8, max_items=4096)
+                                               "three_waves", "two_waves", "two_waves", "one_wave"]
+    b = qoc.Batch(max_contexts=12, max_items=4096)
     b.run(systems)
     torch.cuda.synchronize()
     _check_equal_to_solo(members, systems)
@@ -181,7 +184,7 @@ def test_tuner_choices_are_valid_and_keep_bit_identity():
     assert all(ms > 0 for ms in r["backward_ms"].values()) and len(r["backward_ms"]) == 3
     r3 = autotune.tune_system(systems[3], reps=1, warmup=1)          # a multi-column layout: two schedules
     assert r3["choice"] in ("one_wave", "two_waves") and list(r3["backward_ms"]) == ["one_wave", "two_waves"]
-    b = qoc.Batch(max_contexts=8, max_items=4096)
+    b = qoc.Batch(max_contexts=12, max_items=4096)
     rb = autotune.tune_batch(b, systems, reps=2)
     keys = {autotune.group_key(s) for s in systems if len(s.schedules()) > 1}
     assert set(rb["choice"]) == keys
