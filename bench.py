@@ -341,6 +341,11 @@ def main():
                     help="window-state scale(s) sigma of the optimisation runs, comma-separated (Sec. 5 scans "
                          "0.05..0.15 per case; 0.05 needed the fewest iterations on every QFT case)")
     ap.add_argument("--dipole-steps", type=int, default=10, help="timed steps of the dipole systems (0: skip)")
+    ap.add_argument("--windows", type=int, default=0,
+                    help="window count of the 4-qubit system (0: its configured 128; other values change the "
+                         "workload the line reports)")
+    ap.add_argument("--schedule", default="auto", choices=["auto", "one_wave", "two_waves", "three_waves"],
+                    help="backward schedule of the 4-qubit system (qoc_set_schedule)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -356,16 +361,19 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     w = WL.c3()
+    if args.windows > 0:
+        w = w.replace(n_windows=args.windows)
     alpha_np = WL.gen_alpha(w, args.seed)
     alpha = torch.tensor(alpha_np, device=dev)
 
-    def make(precision):
-        s = qoc.System(w, precision=precision)
+    def make(precision, schedule="auto"):
+        s = qoc.System(w, precision=precision, backward_schedule=schedule)
         s.set_controls(alpha)
         return s
 
     log(f"workload {w.name}: N={w.N} E={w.E} N_T={w.n_steps} M={w.n_windows} d={w.d}")
-    s = make(args.precision)
+    s = make(args.precision, args.schedule)
+    schedule = s.schedule()
     t0 = time.perf_counter()
     Wt, _ = s.rollout(device=True)
     noise = torch.tensor(WL.gen_noise(w, args.seed), device=dev)
@@ -408,7 +416,8 @@ def main():
     flops = f_bwd if dominant == "backward" else f_fwd
     achieved = flops / (tm[dominant] * 1e-3) / 1e12
     tname = "float" if args.precision == "fp32" else "double"
-    kname = (f"k_backward<{tname}, 4, 4, 3, false>" if dominant == "backward"
+    bkernel = {"one_wave": "k_backward", "two_waves": "k_backward_xw", "three_waves": "k_backward_x3"}[schedule]
+    kname = (f"{bkernel}<{tname}, 4, 4, 3, false>" if dominant == "backward"
              else f"k_forward<{tname}, 4, 4, 3, false, false>")
     value = args.steps / elapsed
     result = {
@@ -427,7 +436,7 @@ def main():
         "config": {"workload": f"4-qubit QFT-shaped system q=4 L=4 N=256 E=16 N_T={w.n_steps} M={w.n_windows} "
                                f"d={w.d} window-state vars={2 * w.n_w}",
                    "propagation": args.precision, "reductions": "f64", "fixed_point_iters": kit,
-                   "checkpoint_every": w.checkpoint_every},
+                   "checkpoint_every": w.checkpoint_every, "backward_schedule": schedule},
         "window_steps_per_s": value * 2 * w.n_steps,
         "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
         "phases_ms": {k: tm[k] for k in qoc.PHASES},
@@ -436,7 +445,7 @@ def main():
                      "peak": PEAK_FP32_VECTOR_TFLOPS if args.precision == "fp32" else PEAK_FP64_VECTOR_TFLOPS,
                      "unit": "TFLOP/s",
                      "frac": achieved / (PEAK_FP32_VECTOR_TFLOPS if args.precision == "fp32" else PEAK_FP64_VECTOR_TFLOPS),
-                     "traffic": measured_traffic(kname),
+                     "traffic": measured_traffic(kname) if w.n_windows == WL.c3().n_windows else None,
                      "flops_per_launch": flops, "mean_launch_ms": tm[dominant]},
         "P": float(P.item()),
         "paper_context": "context only, not a target: the paper reports speedup ratios, not rates; one gradient of "
