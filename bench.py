@@ -8,7 +8,7 @@ sweep, gradient projection onto the controls and the window-state gradient.
 Inputs (controls, window states = GPU roll-out + seeded noise) are resident in
 HBM before the timed region; outputs stay on the device.
 
-Prints ONE JSON line (rank 0).  --gpus > 1 is rejected: this build runs on one GPU.
+Prints ONE JSON line (rank 0).  --gpus > 1 is rejected: the library runs on one GPU.
 """
 from __future__ import annotations
 
