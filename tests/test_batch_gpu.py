@@ -118,6 +118,46 @@ def test_full_mix_64_evaluations_equal_solo():
         assert P == P0 and np.array_equal(ga, ga0) and np.array_equal(gW, gW0), (idx, w.name, w.n_windows)
 
 
+@pytest.mark.timeout(900)
+def test_full_mix_64_evaluations_match_oracle():
+    """Each evaluation of the 64-eval mix against the FP64 oracle: the whole objective and gradient
+    for the 2- and 3-qubit members; for the 4-qubit members (up to 25,000-step windows) the
+    penalty of window 1 and dP/dW^1 from window-local oracle runs of windows 1 and 2."""
+    import time
+    mix = WL.batch_mix(7)
+    systems, inputs = [], []
+    for e in mix:
+        w = e["workload"]
+        a, W = make_inputs(w, e["seed"])
+        s = qoc.System(w, precision="fp32")
+        load(s, a, W)
+        systems.append(s)
+        inputs.append((w, a, W))
+    b = qoc.Batch(max_contexts=64, max_items=400000)
+    b.run(systems)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    worst = {2: [0.0, 0.0], 3: [0.0, 0.0], 4: [0.0, 0.0]}
+    for (w, a, W), s in zip(inputs, systems):
+        P, t, ga, gW = s.read_results()
+        if w.q < 4:
+            P0, t0_, ga0, gW0 = O.gradient(w, a, W)
+            g = np.concatenate([ga, gW.view(np.float64).ravel()])
+            g0 = np.concatenate([ga0, gW0.view(np.float64).ravel()])
+            eP, eg = abs(P - P0) / abs(P0), np.linalg.norm(g - g0) / np.linalg.norm(g0)
+            assert eP <= 1e-5 and eg <= 1e-4, (w.name, w.n_windows, eP, eg)
+        else:
+            piece = O.windows(w, a, W, 1, 2)
+            eP = abs(t[5] - piece["pen"][0]) / piece["pen"][0]
+            g_ref = w.mu * (W[0] - piece["Ufin"][0]) - 2 * piece["lam0"][1]
+            eg = np.linalg.norm(gW[0] - g_ref) / np.linalg.norm(g_ref)
+            assert eP <= 1e-3 and eg <= 1e-4, (w.name, w.n_windows, eP, eg)
+        worst[w.q] = [max(worst[w.q][0], eP), max(worst[w.q][1], eg)]
+        s.close()
+    print(f"worst errors by qubits (objective or penalty, gradient): {worst}; oracle {time.time() - t0:.1f} s",
+          flush=True)
+
+
 def test_batch_argument_errors():
     w, a, W = small_mix(3)[0]
     s1 = qoc.System(w, precision="fp32")
