@@ -146,23 +146,38 @@ def bench_batch(seed, reps, log):
     return out
 
 
-def bench_serve(rate, n_requests, plain_requests, seed, budget_gb, log, schedules=None):
-    """Open-loop Poisson trace through the continuous-batching server, and the plain FP64
-    per-request path on the first `plain_requests` requests of the same trace."""
+def serve_trace(rate, n_requests, seed, budget_gb, log, schedules=None):
+    """One open-loop Poisson trace through the continuous-batching server (FP32 propagation)."""
     import numpy as np
     from paper_2407_13950_amd import serve
-    out = {"rate_rps": rate, "requests": n_requests, "runs": 64, "objective_only": 0.1,
-           "hbm_budget_GB": budget_gb}
     runs, reqs, counts = serve.make_trace(n_requests, rate=rate, seed=seed, n_runs=64)
     be = serve.QocBackend(precision="fp32", n_streams=4, max_batch=64, max_items=400000, schedules=schedules)
-    out["backward_schedules"] = dict(schedules or {})
     srv = serve.Server(be, hbm_budget=int(budget_gb * (1 << 30)), max_batch=64)
     for r, w in runs.items():
         srv.register_run(r, w, counts[r], initial=serve.initial_inputs(w, 1000 + r))
     summ = srv.run_trace(reqs, progress=lambda d, n: log(f"serve: {d}/{n} done"))
-    out["batched_fp32"] = dict(summ, batches=srv.batches, mean_batch=float(np.mean(srv.batch_sizes)),
-                               peak_hbm_GB=srv.peak_used / (1 << 30))
+    return dict(summ, batches=srv.batches, mean_batch=float(np.mean(srv.batch_sizes)),
+                peak_hbm_GB=srv.peak_used / (1 << 30))
+
+
+def bench_serve(rate, n_requests, plain_requests, seed, budget_gb, log, schedules=None, sweep=(), mix_rate=None):
+    """Open-loop Poisson trace through the continuous-batching server, the plain FP64 per-request
+    path on the first `plain_requests` requests of the same trace, and optionally the server at
+    other loads (fractions of `mix_rate`)."""
+    from paper_2407_13950_amd import serve
+    out = {"rate_rps": rate, "requests": n_requests, "runs": 64, "objective_only": 0.1,
+           "hbm_budget_GB": budget_gb, "backward_schedules": dict(schedules or {})}
+    summ = serve_trace(rate, n_requests, seed, budget_gb, log, schedules)
+    out["batched_fp32"] = summ
     log(f"serve fp32: {summ['throughput_rps']:.1f} req/s p50 {summ['p50_ms']:.2f} ms p99 {summ['p99_ms']:.2f} ms")
+    if sweep and mix_rate:
+        out["load_sweep"] = []
+        for f in sweep:
+            sm = serve_trace(f * mix_rate, n_requests, seed, budget_gb, log, schedules)
+            out["load_sweep"].append({"load": f, "rate_rps": f * mix_rate, "throughput_rps": sm["throughput_rps"],
+                                      "p50_ms": sm["p50_ms"], "p99_ms": sm["p99_ms"], "mean_batch": sm["mean_batch"]})
+            log(f"serve fp32 at {f:.2f} x mix rate: {sm['throughput_rps']:.1f} req/s p50 {sm['p50_ms']:.2f} ms "
+                f"p99 {sm['p99_ms']:.2f} ms")
     if plain_requests > 0:
         runs, reqs, counts = serve.make_trace(n_requests, rate=rate, seed=seed, n_runs=64)
         reqs = reqs[:plain_requests]
@@ -333,6 +348,8 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="arrival rate as a fraction of the batched mix rate under the default schedule rule")
     ap.add_argument("--hbm-budget-gb", type=float, default=6.0)
+    ap.add_argument("--serve-sweep", default="",
+                    help="further serving loads (fractions of the mix rate, comma-separated) run after the main trace")
     ap.add_argument("--opt-runs", default="2:16:3000,2:1:500,3:32:6000,3:1:400",
                     help="optimisation runs on the paper's QFT systems, qubits:windows:iteration-cap, "
                          "comma-separated (empty: skip); e.g. add 4:16:10000 for QFT-16 (~3 min)")
@@ -485,9 +502,11 @@ def main():
             if "serve" in extras:
                 # the server runs the library's default schedule rule: load it relative to the mix's
                 # rate under that rule
-                rate = args.serve_load * 64e3 / result["batched_mix"]["schedule"]["default_rule_ms"]
-                result["serving"] = bench_serve(rate, args.serve_requests, args.serve_plain_requests, args.seed,
-                                                args.hbm_budget_gb, log)
+                mix_rate = 64e3 / result["batched_mix"]["schedule"]["default_rule_ms"]
+                sweep = [float(x) for x in args.serve_sweep.split(",") if x]
+                result["serving"] = bench_serve(args.serve_load * mix_rate, args.serve_requests,
+                                                args.serve_plain_requests, args.seed, args.hbm_budget_gb, log,
+                                                sweep=sweep, mix_rate=mix_rate)
         except Exception as e:   # the headline line must still be printed
             result["extras_error"] = repr(e)
             log(f"extras failed: {e!r}")
