@@ -67,6 +67,19 @@ def test_schedules_on_multi_column_layouts_match_oracle(q, L, n_steps, M, prec, 
         assert abs(P - P0) <= tol_P * abs(P0) and g <= tol_g
 
 
+@pytest.mark.parametrize("q,L,sched", [(4, 4, "one_wave"), (4, 4, "two_waves"), (4, 4, "three_waves"),
+                                        (3, 4, "one_wave"), (3, 4, "two_waves"), (2, 2, "two_waves")])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_schedules_with_a_single_window(q, L, sched, prec):
+    """M = 1: no window states, the only window's terminal condition is the infidelity's."""
+    w, alpha, W = PG.small_case(q, L, 180, 1, seed=6)
+    assert W is None
+    P0, t0, ga0, _ = O.gradient(w, alpha, W)
+    P, t, ga, _ = PG.run_gpu(w, alpha, W, prec, backward_schedule=sched)
+    tol_P, tol_g = TOL[prec]
+    assert abs(P - P0) <= tol_P * abs(P0) and PG.rel(ga, ga0) <= tol_g
+
+
 @pytest.mark.parametrize("sched", ["one_wave", "two_waves", "three_waves"])
 def test_forced_schedules_with_checkpoints_and_one_step_windows(sched):
     """Checkpoint re-syncs inside windows, and windows of a single step."""
