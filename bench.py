@@ -25,6 +25,8 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_VECTOR_TFLOPS = 157.3      # MI355X published FP32 vector peak (plain FP32 FMAs reach it: two per SIMD per 4 clocks)
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+# the backward kernel of each schedule (qoc_set_schedule); two wavefronts run k_backward_xw on every layout
+BACKWARD_KERNEL = {"one_wave": "k_backward", "two_waves": "k_backward_xw", "three_waves": "k_backward_x3"}
 
 
 def log(msg):
@@ -284,7 +286,9 @@ def bench_dipole(steps, warmup, seed, log):
                      "value": nst / el, "unit": "evals/s", "steps": nst,
                      "fixed_point_iters": tm["fixed_point_iters"],
                      "phases_ms": {k: tm[k] for k in qoc.PHASES},
-                     "roofline": {"kernel": f"k_backward<float, {w.q}, {w.L}, {s.info['lane_digits']}, true>",
+                     "backward_schedule": s.schedule(),
+                     "roofline": {"kernel": f"{BACKWARD_KERNEL[s.schedule()]}<float, {w.q}, {w.L}, "
+                                            f"{s.info['lane_digits']}, true>",
                                   "bound": "alu", "achieved": ach, "peak": PEAK_FP32_VECTOR_TFLOPS,
                                   "unit": "TFLOP/s", "frac": ach / PEAK_FP32_VECTOR_TFLOPS}}
         log(f"dipole {name}: {nst / el:.1f} evals/s, backward {tm['backward']:.3f} ms, "
@@ -433,8 +437,7 @@ def main():
     flops = f_bwd if dominant == "backward" else f_fwd
     achieved = flops / (tm[dominant] * 1e-3) / 1e12
     tname = "float" if args.precision == "fp32" else "double"
-    bkernel = {"one_wave": "k_backward", "two_waves": "k_backward_xw", "three_waves": "k_backward_x3"}[schedule]
-    kname = (f"{bkernel}<{tname}, 4, 4, 3, false>" if dominant == "backward"
+    kname = (f"{BACKWARD_KERNEL[schedule]}<{tname}, 4, 4, 3, false>" if dominant == "backward"
              else f"k_forward<{tname}, 4, 4, 3, false, false>")
     value = args.steps / elapsed
     result = {
