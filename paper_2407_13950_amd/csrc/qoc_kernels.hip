@@ -328,6 +328,71 @@ struct LaneGets {
   }
 };
 
+// Two-level layouts: the neighbour of a lane along a lane digit of stride ST (1, 2, 4
+// or 8, within a row of 16 lanes) is lane ^ ST, whichever way the digit steps (the
+// other direction meets a zero weight).  DPP moves read it straight from that lane's
+// register: xor 1 and 2 are quad permutations, xor 4 mirrors each half row and then
+// reverses each quad ((i ^ 7) ^ 3 = i ^ 4), xor 8 rotates the row by 8.  No LDS round
+// trip.
+// The dipole pairs of adjacent digits read lane ^ (st_j | st_j+1): xor 3 reverses each
+// quad, xor 6 mirrors each half row and swaps neighbours ((i ^ 7) ^ 1), xor 12 mirrors
+// the row and reverses each quad ((i ^ 15) ^ 3).
+template <int M>
+__device__ __forceinline__ float lane_xor(float v) {
+  constexpr int QP1 = 0xB1, QP2 = 0x4E, QP3 = 0x1B;     // quad_perm [1,0,3,2], [2,3,0,1], [3,2,1,0]
+  constexpr int HMIR = 0x141, MIR = 0x140, ROR8 = 0x128; // row_half_mirror, row_mirror, row_ror:8
+  int x = __float_as_int(v);
+  if constexpr (M == 1) {
+    x = __builtin_amdgcn_update_dpp(0, x, QP1, 0xF, 0xF, true);
+  } else if constexpr (M == 2) {
+    x = __builtin_amdgcn_update_dpp(0, x, QP2, 0xF, 0xF, true);
+  } else if constexpr (M == 3) {
+    x = __builtin_amdgcn_update_dpp(0, x, QP3, 0xF, 0xF, true);
+  } else if constexpr (M == 4) {
+    x = __builtin_amdgcn_update_dpp(0, x, HMIR, 0xF, 0xF, true);
+    x = __builtin_amdgcn_update_dpp(0, x, QP3, 0xF, 0xF, true);
+  } else if constexpr (M == 6) {
+    x = __builtin_amdgcn_update_dpp(0, x, HMIR, 0xF, 0xF, true);
+    x = __builtin_amdgcn_update_dpp(0, x, QP1, 0xF, 0xF, true);
+  } else if constexpr (M == 8) {
+    x = __builtin_amdgcn_update_dpp(0, x, ROR8, 0xF, 0xF, true);
+  } else {
+    static_assert(M == 12, "lane xor beyond a row of 16 lanes");
+    x = __builtin_amdgcn_update_dpp(0, x, MIR, 0xF, 0xF, true);
+    x = __builtin_amdgcn_update_dpp(0, x, QP3, 0xF, 0xF, true);
+  }
+  return __int_as_float(x);
+}
+
+// The lane exchange (and the dipole terms' reads) run through DPP for FP32 two-level
+// layouts with at most four lane digits, with no LDS records at all.
+template <typename T, int L, int LD>
+__device__ __forceinline__ constexpr bool dpp_layout() {
+  return sizeof(T) == 4 && L == 2 && LD >= 1 && LD <= 4;
+}
+
+template <int M, typename T, int NV>
+__device__ __forceinline__ void xor_record(const T *own, T *out) {
+#pragma unroll
+  for (int i = 0; i < NV; ++i) out[i] = lane_xor<M>(own[i]);
+}
+
+template <typename T, int LD, int K, int JJ>
+struct DppGets {
+  template <typename G>
+  __device__ __forceinline__ static void load(const T *rec, T (*n)[2 * K]) {
+    if constexpr (JJ < LD) {
+      constexpr int ST = G::lstride(JJ);
+#pragma unroll
+      for (int i = 0; i < 2 * K; ++i) {
+        n[2 * JJ][i] = lane_xor<ST>(rec[i]);
+        n[2 * JJ + 1][i] = n[2 * JJ][i];
+      }
+      DppGets<T, LD, K, JJ + 1>::template load<G>(rec, n);
+    }
+  }
+};
+
 // Writes this lane's K complex values to the exchange.  FP32 also requests all
 // neighbours' records at once (n[2jj]: lane digit jj one step up, n[2jj+1]: one
 // step down), so their latencies overlap with the lane-independent work the caller
@@ -349,6 +414,10 @@ __device__ __forceinline__ void lane_exchange(const Lane<T, Q, L, LD> &ln, const
     for (int o = 0; o < K; ++o) {
       rec[2 * o] = vr[o];
       rec[2 * o + 1] = vi[o];
+    }
+    if constexpr (dpp_layout<T, L, LD>()) {
+      DppGets<T, LD, K, 0>::template load<Geo<T, Q, L, LD>>(rec, n);
+      return;
     }
     xput<T, 2 * K>(ln.xb, ln.lane, rec);
     if constexpr (KO > 0) {
@@ -380,10 +449,18 @@ __device__ __forceinline__ void lane_digit_terms(const Lane<T, Q, L, LD> &ln, co
     }
     const T *up = XPre<T>::value ? n[2 * JJ] : n[0];
     const T *dn = XPre<T>::value ? n[2 * JJ + 1] : n[1];
+    if constexpr (dpp_layout<T, L, LD>()) {
+      // two levels: up and dn are the same lane and one of the two weights is zero, so
+      // one product with their sum gives the same value (half the multiply-adds)
+      const T cr = lor[JJ] + hir[JJ], ci = loi[JJ] + hii[JJ];
 #pragma unroll
-    for (int o = 0; o < K; ++o) {
-      cmac(Sr[o], Si[o], lor[JJ], loi[JJ], up[2 * o], up[2 * o + 1]);
-      cmac(Sr[o], Si[o], hir[JJ], hii[JJ], dn[2 * o], dn[2 * o + 1]);
+      for (int o = 0; o < K; ++o) cmac(Sr[o], Si[o], cr, ci, up[2 * o], up[2 * o + 1]);
+    } else {
+#pragma unroll
+      for (int o = 0; o < K; ++o) {
+        cmac(Sr[o], Si[o], lor[JJ], loi[JJ], up[2 * o], up[2 * o + 1]);
+        cmac(Sr[o], Si[o], hir[JJ], hii[JJ], dn[2 * o], dn[2 * o + 1]);
+      }
     }
     lane_digit_terms<T, Q, L, LD, K, JJ + 1>(ln, lor, loi, hir, hii, n, Sr, Si);
   } else if constexpr (LD > 0 && !XPre<T>::value) {
@@ -413,28 +490,47 @@ template <int HALF>
 __device__ __forceinline__ constexpr int lead_dn(int s0, int b) { return s0 - 1 + b >= 0 ? s0 - 1 + b : s0; }
 
 template <typename T, int Q, int L, int LD, int C, int NRHS, int JJ>
-__device__ __forceinline__ void hop_lane_pairs(const Lane<T, Q, L, LD> &ln, const T *base, T *Sr, T *Si) {
+__device__ __forceinline__ void hop_lane_pairs(const Lane<T, Q, L, LD> &ln, const T *base, const T *own, T *Sr,
+                                               T *Si) {
   using G = Geo<T, Q, L, LD>;
   if constexpr (JJ + 1 < LD) {
     constexpr int NO = C >= 0 ? G::H : G::EPL;
     constexpr int NV = 2 * NO * NRHS;
     constexpr int OFF = G::lstride(JJ) - G::lstride(JJ + 1);   // A: l_jj + 1, l_jj+1 - 1
     T a[NV], b[NV];
-    xget<T, NV, OFF>(base, ln.lane, a);
-    xget<T, NV, -OFF>(base, ln.lane, b);
+    if constexpr (dpp_layout<T, L, LD>()) {     // two levels: A and B both read lane ^ (st_jj | st_jj+1)
+      xor_record<G::lstride(JJ) + G::lstride(JJ + 1), T, NV>(own, a);
 #pragma unroll
-    for (int i = 0; i < NO * NRHS; ++i) {
-      Sr[i] = fma_(ln.hla[JJ], a[2 * i], Sr[i]);
-      Si[i] = fma_(ln.hla[JJ], a[2 * i + 1], Si[i]);
-      Sr[i] = fma_(ln.hlb[JJ], b[2 * i], Sr[i]);
-      Si[i] = fma_(ln.hlb[JJ], b[2 * i + 1], Si[i]);
+      for (int i = 0; i < NV; ++i) b[i] = a[i];
+    } else {
+      xget<T, NV, OFF>(base, ln.lane, a);
+      xget<T, NV, -OFF>(base, ln.lane, b);
     }
-    hop_lane_pairs<T, Q, L, LD, C, NRHS, JJ + 1>(ln, base, Sr, Si);
+    if constexpr (dpp_layout<T, L, LD>()) {     // same operand, one of the weights zero: one product
+      const T w = ln.hla[JJ] + ln.hlb[JJ];
+#pragma unroll
+      for (int i = 0; i < NO * NRHS; ++i) {
+        Sr[i] = fma_(w, a[2 * i], Sr[i]);
+        Si[i] = fma_(w, a[2 * i + 1], Si[i]);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NO * NRHS; ++i) {
+        Sr[i] = fma_(ln.hla[JJ], a[2 * i], Sr[i]);
+        Si[i] = fma_(ln.hla[JJ], a[2 * i + 1], Si[i]);
+        Sr[i] = fma_(ln.hlb[JJ], b[2 * i], Sr[i]);
+        Si[i] = fma_(ln.hlb[JJ], b[2 * i + 1], Si[i]);
+      }
+    }
+    hop_lane_pairs<T, Q, L, LD, C, NRHS, JJ + 1>(ln, base, own, Sr, Si);
   }
 }
 
+// base: the LDS records of the lane exchange; own: this lane's record values (the same
+// layout), from which the two-level layouts shuffle the partner lanes' through DPP.
 template <typename T, int Q, int L, int LD, int C, int NRHS>
-__device__ __forceinline__ void hop_terms(const Lane<T, Q, L, LD> &ln, const T *base, T *Sr, T *Si) {
+__device__ __forceinline__ void hop_terms(const Lane<T, Q, L, LD> &ln, const T *base, const T *own, T *Sr,
+                                          T *Si) {
   using G = Geo<T, Q, L, LD>;
   constexpr bool RBL = C >= 0;
   constexpr int NO = RBL ? G::H : G::EPL;
@@ -448,8 +544,14 @@ __device__ __forceinline__ void hop_terms(const Lane<T, Q, L, LD> &ln, const T *
     {
       constexpr int ST = G::lstride(0);
       T dn[NV], up[NV];
-      xget<T, NV, -ST>(base, ln.lane, dn);
-      xget<T, NV, ST>(base, ln.lane, up);
+      if constexpr (dpp_layout<T, L, LD>()) {   // two levels: both read lane ^ ST
+        xor_record<ST, T, NV>(own, dn);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) up[i] = dn[i];
+      } else {
+        xget<T, NV, -ST>(base, ln.lane, dn);
+        xget<T, NV, ST>(base, ln.lane, up);
+      }
 #pragma unroll
       for (int o = 0; o < NO; ++o) {
 #pragma unroll
@@ -464,10 +566,15 @@ __device__ __forceinline__ void hop_terms(const Lane<T, Q, L, LD> &ln, const T *
             const T ar = bl ? dn[2 * ia1] : dn[2 * ia0], ai = bl ? dn[2 * ia1 + 1] : dn[2 * ia0 + 1];
             const T br = bl ? up[2 * ib1] : up[2 * ib0], bi = bl ? up[2 * ib1 + 1] : up[2 * ib0 + 1];
             const T wa = ln.hsa * ln.wup[beta][s0], wb = ln.hsb * ln.wdn[beta][s0];
-            Sr[so] = fma_(wa, ar, Sr[so]);
-            Si[so] = fma_(wa, ai, Si[so]);
-            Sr[so] = fma_(wb, br, Sr[so]);
-            Si[so] = fma_(wb, bi, Si[so]);
+            if constexpr (dpp_layout<T, L, LD>()) {   // two levels: one slot, one partner lane, one weight
+              Sr[so] = fma_(wa + wb, ar, Sr[so]);
+              Si[so] = fma_(wa + wb, ai, Si[so]);
+            } else {
+              Sr[so] = fma_(wa, ar, Sr[so]);
+              Si[so] = fma_(wa, ai, Si[so]);
+              Sr[so] = fma_(wb, br, Sr[so]);
+              Si[so] = fma_(wb, bi, Si[so]);
+            }
           } else {                              // plain layout: slot o holds register digit o
             const int la = o;
             if (la < L - 1) {
@@ -486,8 +593,8 @@ __device__ __forceinline__ void hop_terms(const Lane<T, Q, L, LD> &ln, const T *
         }
       }
     }
-    hop_lane_pairs<T, Q, L, LD, C, NRHS, 0>(ln, base, Sr, Si);
-    wave_sync();
+    hop_lane_pairs<T, Q, L, LD, C, NRHS, 0>(ln, base, own, Sr, Si);
+    if constexpr (!dpp_layout<T, L, LD>()) wave_sync();
   }
 }
 
@@ -519,7 +626,15 @@ __device__ __forceinline__ void apply_Hc(const Lane<T, Q, L, LD> &ln, const T *c
     }
   }
   lane_digit_terms<T, Q, L, LD, G::EPL>(ln, lor, loi, hir, hii, n, Sr, Si);
-  if constexpr (HOP) hop_terms<T, Q, L, LD, -1, 1>(ln, ln.xb, Sr, Si);   // reads the record above
+  if constexpr (HOP) {                    // reads the record above
+    T own[2 * G::EPL];
+#pragma unroll
+    for (int e = 0; e < G::EPL; ++e) {
+      own[2 * e] = vr[e];
+      own[2 * e + 1] = vi[e];
+    }
+    hop_terms<T, Q, L, LD, -1, 1>(ln, ln.xb, own, Sr, Si);
+  }
 }
 
 // Per-step control coefficients: c'_j for register digits, per-lane lowering
@@ -623,8 +738,14 @@ __device__ __forceinline__ void apply_half_regs(const Lane<T, Q, L, LD> &ln, con
       const int o = s0 * G::RT + t;
       Sr[o] = 0;
       Si[o] = 0;
-      cmac(Sr[o], Si[o], cf.ur[beta][s0], cf.ui[beta][s0], pr[s0 + 1], pi[s0 + 1]);
-      cmac_conj(Sr[o], Si[o], cf.dr[beta][s0], cf.di[beta][s0], pr[s0], pi[s0]);
+      if constexpr (L == 2) {
+        // two levels: both operands are the one input slot and one weight is zero, so
+        // one product with c_up + conj(c_dn) gives the same value
+        cmac(Sr[o], Si[o], cf.ur[beta][s0] + cf.dr[beta][s0], cf.ui[beta][s0] - cf.di[beta][s0], pr[s0], pi[s0]);
+      } else {
+        cmac(Sr[o], Si[o], cf.ur[beta][s0], cf.ui[beta][s0], pr[s0 + 1], pi[s0 + 1]);
+        cmac_conj(Sr[o], Si[o], cf.dr[beta][s0], cf.di[beta][s0], pr[s0], pi[s0]);
+      }
     }
   }
 #pragma unroll
@@ -659,7 +780,15 @@ __device__ __forceinline__ void apply_half(const Lane<T, Q, L, LD> &ln, const Co
   lane_exchange<T, Q, L, LD, G::H, HOP ? G::H : 0>(ln, vr + IN, vi + IN, n, owr, owi);
   apply_half_regs<T, Q, L, LD, C>(ln, cf, vr, vi, Sr, Si);
   lane_digit_terms<T, Q, L, LD, G::H>(ln, cf.lor, cf.loi, cf.hir, cf.hii, n, Sr, Si);
-  if constexpr (HOP) hop_terms<T, Q, L, LD, C, 1>(ln, ln.xb + xtail<T, G::H>(), Sr, Si);
+  if constexpr (HOP) {
+    T own[2 * G::H];
+#pragma unroll
+    for (int o = 0; o < G::H; ++o) {
+      own[2 * o] = owr[o];
+      own[2 * o + 1] = owi[o];
+    }
+    hop_terms<T, Q, L, LD, C, 1>(ln, ln.xb + xtail<T, G::H>(), own, Sr, Si);
+  }
 }
 
 __device__ __forceinline__ int kit_of(const DevSys &s) { return s.kit_fixed > 0 ? s.kit_fixed : *s.kit; }
@@ -831,7 +960,15 @@ __device__ __forceinline__ void half_sweep2(const Lane<T, Q, L, LD> &ln, const C
   apply_half_regs<T, Q, L, LD, C>(ln, cf, var, vai, Sr, Si);
   apply_half_regs<T, Q, L, LD, C>(ln, cf, vbr, vbi, Sr + G::H, Si + G::H);
   lane_digit_terms<T, Q, L, LD, 2 * G::H>(ln, cf.lor, cf.loi, cf.hir, cf.hii, n, Sr, Si);
-  if constexpr (HOP) hop_terms<T, Q, L, LD, C, 2>(ln, ln.xb + xtail<T, 2 * G::H>(), Sr, Si);
+  if constexpr (HOP) {
+    T own[4 * G::H];
+#pragma unroll
+    for (int o = 0; o < 2 * G::H; ++o) {
+      own[2 * o] = orr[o];
+      own[2 * o + 1] = ori[o];
+    }
+    hop_terms<T, Q, L, LD, C, 2>(ln, ln.xb + xtail<T, 2 * G::H>(), own, Sr, Si);
+  }
 #pragma unroll
   for (int o = 0; o < G::H; ++o) {
     jacobi_update<T, Q, L, LD, REV>(ln, OUT + o, Sr[o], Si[o], xar[OUT + o], xai[OUT + o], war[OUT + o], wai[OUT + o]);
