@@ -19,6 +19,10 @@ from paper_2407_13950_amd.autograd import penalty_objective
 
 pytestmark = pytest.mark.gpu
 
+# Per-window penalty tolerance of FP32 propagation, derived in tests/test_longwindow_gpu.py
+# (random-walk rounding model: predicts 4e-8 at these 781-step windows).
+PEN_RTOL_FP32 = 1e-6
+
 
 def rel(a, b):
     a, b = np.asarray(a), np.asarray(b)
@@ -93,12 +97,14 @@ def test_c3_full_size_matches_oracle(c3_problem, prec, sched):
     w, alpha, W, (P0, t0, ga0, gW0) = c3_problem
     P, terms, ga, gW = gpu_gradient(w, alpha, W, prec, sched)
     e = report(f"{w.name} {sched}", prec, P, P0, ga, ga0, gW, gW0)
-    pen_rel = np.max(np.abs(terms[4:] - t0[4:]) / np.abs(t0[4:]))
-    print(f"  per-window penalty max rel err {pen_rel:.2e}", flush=True)
+    pen_rel = np.max(np.abs(terms[5:] - t0[5:]) / np.abs(t0[5:]))      # |C^m|^2, m = 1..M-1
+    g_rel = abs(complex(*terms[3:5]) - complex(*t0[3:5])) / abs(complex(*t0[3:5]))
+    print(f"  per-window penalty max rel err {pen_rel:.2e}, gamma rel err {g_rel:.2e}", flush=True)
     if prec == "fp64":
-        assert e["P"] <= 1e-11 and e["grad"] <= 1e-10 and pen_rel <= 1e-9
+        assert e["P"] <= 1e-11 and e["grad"] <= 1e-10 and pen_rel <= 1e-9 and g_rel <= 1e-10
     else:
-        assert e["P"] <= 1e-5 and e["grad"] <= 1e-4 and pen_rel <= 1e-3
+        assert e["P"] <= 1e-5 and e["grad"] <= 1e-4 and e["alpha"] <= 1e-4 and pen_rel <= PEN_RTOL_FP32
+        assert g_rel <= 1e-5
 
 
 def test_c3_sampled_windows_match_oracle_pieces(c3_problem):
@@ -125,6 +131,7 @@ def test_c3_central_differences_fp64():
     gnorm = np.linalg.norm(flat(ga, gW))
     h = 1e-6
     worst = 0.0
+    rows = []
     for v in WL.gen_directions(w, 10, 20):
         s.set_controls(alpha + h * v["alpha"])
         s.set_window_states(W + h * v["W"])
@@ -135,7 +142,11 @@ def test_c3_central_differences_fp64():
         fd = (Pp - Pm) / (2 * h)
         an = float(ga @ v["alpha"] + np.sum(gW.real * v["W"].real + gW.imag * v["W"].imag))
         worst = max(worst, abs(fd - an) / (abs(an) + 1e-3 * gnorm))
-    print(f"C3 FD worst scaled error {worst:.2e} (|grad| = {gnorm:.3e})", flush=True)
+        rows.append((abs(fd - an), abs(an)))
+    rows = np.array(rows)
+    print(f"C3 FD worst scaled error {worst:.2e} (|grad| = {gnorm:.3e}, P = {P:.6f}); |fd - an| max "
+          f"{rows[:, 0].max():.2e}, median {np.median(rows[:, 0]):.2e}; |fd - an|/|an| max "
+          f"{(rows[:, 0] / rows[:, 1]).max():.2e}; |an| min {rows[:, 1].min():.2e}", flush=True)
     assert worst <= 1e-5
 
 
