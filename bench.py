@@ -73,26 +73,115 @@ def percentile(xs, p):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def cpu_baseline(w, alpha, seconds):
-    """The FP64 CPU oracle timed on a bounded sample of the same workload: the forward and
-    adjoint work of the first nw windows (all columns), scaled to one whole evaluation."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def rel_errors(res, ref):
+    """Relative errors of one evaluation (P, terms, grad_alpha, grad_W) against the oracle's."""
+    import numpy as np
+    P, t, ga, gW = res
+    P0, t0, ga0, gW0 = ref
+
+    def rl2(a, b):
+        a, b = np.asarray(a).ravel(), np.asarray(b).ravel()
+        return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    g = np.concatenate([ga, np.asarray(gW).view(np.float64).ravel()])
+    g0 = np.concatenate([ga0, np.asarray(gW0).view(np.float64).ravel()])
+    out = {"P_rel": abs(P - P0) / abs(P0), "J_rel": abs(t[0] - t0[0]) / abs(t0[0]), "grad_rel_l2": rl2(g, g0),
+           "grad_alpha_rel_l2": rl2(ga, ga0), "grad_W_rel_l2": rl2(gW, gW0) if np.size(gW0) else 0.0}
+    if len(t0) > 5:
+        out["window_penalty_max_rel"] = float(np.max(np.abs(t[5:] - t0[5:]) / np.abs(t0[5:])))
+    return out
+
+
+def gpu_eval(w, alpha, W, precision, schedule="auto"):
+    """One objective+gradient evaluation through the C ABI with host inputs and outputs."""
+    from paper_2407_13950_amd import qoc
+    s = qoc.System(w, precision=precision, backward_schedule=schedule)
+    s.set_controls(alpha)
+    s.set_window_states(W)
+    out = s.gradient()
+    s.close()
+    return out
+
+
+def single_thread_sample(w, alpha):
+    """Wall seconds of the oracle's forward and adjoint work for window 1 (all columns) on one
+    thread, in a child process (OMP_NUM_THREADS=1); the cost does not depend on W's values."""
+    import subprocess
+    code = ("import sys, time; sys.path.insert(0, %r)\n"
+            "from oracle import oracle as O\n"
+            "from paper_2407_13950_amd import workloads as WL\n"
+            "w = WL.c3().replace(n_windows=%d)\n"
+            "a = WL.gen_alpha(w, %d); W = WL.gen_qr_states(w, 7)\n"
+            "t0 = time.perf_counter(); O.windows(w, a, W, 1, 1); print(time.perf_counter() - t0, O.max_threads())\n"
+            ) % (ROOT, w.n_windows, 0)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+    if out.returncode != 0:
+        raise RuntimeError(out.stderr[-2000:])
+    t, thr = out.stdout.split()[-2:]
+    return float(t), int(thr)
+
+
+def cpu_baseline_and_errors(w, alpha, noise, schedule, log):
+    """The FP64 CPU oracle on the host cores: one whole evaluation of the 4-qubit system
+    (timed: the CPU baseline) at the bench's controls, with window states = the oracle's own
+    roll-out + the bench's noise (the oracle takes no input from the GPU path).  The GPU
+    evaluates the same point in the bench's configuration (FP32 propagation, same schedule)
+    and in the plain FP64 form; their errors against the oracle are reported.  Also the
+    2- and 3-qubit configurations, and a single-thread sample."""
+    import numpy as np
     from oracle import oracle
     from paper_2407_13950_amd import workloads as WL
-    W = WL.gen_qr_states(w, 7)            # timing only; the oracle's cost does not depend on W's values
+    threads = oracle.max_threads()
     t0 = time.perf_counter()
-    oracle.windows(w, alpha, W, 1, 1)
-    t1 = time.perf_counter() - t0
-    nw = int(max(1, min(w.n_windows, round(seconds / max(t1, 1e-3)))))
-    log(f"cpu baseline: one window {t1:.2f} s; timing {nw} windows")
+    Wt, _ = oracle.rollout(w, alpha)
+    t_roll = time.perf_counter() - t0
+    W = Wt + noise
+    log(f"cpu baseline: oracle roll-out {t_roll:.1f} s on {threads} threads")
     t0 = time.perf_counter()
-    oracle.windows(w, alpha, W, 1, nw)
-    t = time.perf_counter() - t0
-    per_eval = t * w.n_windows / nw
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": 1.0 / per_eval, "unit": "evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"{nw} of {w.n_windows} windows x {w.E} columns (forward + adjoint), "
-                      f"{t:.1f} s, scaled by {w.n_windows}/{nw}",
-            "seconds_per_eval": per_eval}
+    ref = oracle.gradient(w, alpha, W)
+    t_eval = time.perf_counter() - t0
+    log(f"cpu baseline: one oracle evaluation {t_eval:.1f} s")
+    errors = {"c3_fp32": rel_errors(gpu_eval(w, alpha, W, "fp32", schedule), ref),
+              "c3_fp64": rel_errors(gpu_eval(w, alpha, W, "fp64"), ref)}
+    small = {}
+    for name, mk, seed in (("c1", WL.c1, 31), ("c2", WL.c2, 32)):
+        ws = mk()
+        a = WL.gen_alpha(ws, seed)
+        if ws.window_states == "qr":
+            Ws = WL.gen_qr_states(ws, seed)
+        else:
+            Wr, _ = oracle.rollout(ws, a)
+            Ws = Wr + WL.gen_noise(ws, seed)
+        t0 = time.perf_counter()
+        r = oracle.gradient(ws, a, Ws)
+        small[name] = time.perf_counter() - t0
+        for prec in ("fp64", "fp32"):
+            errors[f"{name}_{prec}"] = rel_errors(gpu_eval(ws, a, Ws, prec), r)
+    for k, e in errors.items():
+        log(f"error vs oracle {k}: P {e['P_rel']:.2e}  grad {e['grad_rel_l2']:.2e}")
+    t1, thr1 = single_thread_sample(w, alpha)
+    log(f"cpu baseline: window 1 on one thread {t1:.1f} s")
+    base = {"value": 1.0 / t_eval, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"one whole objective+gradient evaluation of the 4-qubit system ({w.n_windows} windows x "
+                      f"{w.E} columns, forward and adjoint, N_T={w.n_steps}) at the bench's controls and the "
+                      f"oracle's roll-out states + the bench's noise: {t_eval:.1f} s",
+            "seconds_per_eval": t_eval, "window_steps_per_s": 2 * w.n_steps / t_eval,
+            "cpu_model": cpu_model(), "rollout_s": t_roll,
+            "single_thread": {"seconds_window_1": t1, "threads": thr1,
+                              "seconds_per_eval_est": t1 * w.n_windows,
+                              "sample": "window 1 (all 16 columns, forward + adjoint) on one thread, x M"},
+            "c1_seconds_per_eval": small["c1"], "c2_seconds_per_eval": small["c2"]}
+    return base, errors
 
 
 def bench_batch(seed, reps, log):
@@ -162,11 +251,28 @@ def serve_trace(rate, n_requests, seed, budget_gb, log, schedules=None):
                 peak_hbm_GB=srv.peak_used / (1 << 30))
 
 
-def bench_serve(rate, n_requests, plain_requests, seed, budget_gb, log, schedules=None, sweep=(), mix_rate=None):
-    """Open-loop Poisson trace through the continuous-batching server, the plain FP64 per-request
-    path on the first `plain_requests` requests of the same trace, and optionally the server at
-    other loads (fractions of `mix_rate`)."""
+def plain_trace(rate, n_requests, seed, budget_gb, log, burst=False):
+    """The plain FP64 per-request path (one request at a time, single-context calls) on the
+    trace; burst=True makes every request arrive at once (closed loop: its capacity)."""
     from paper_2407_13950_amd import serve
+    runs, reqs, counts = serve.make_trace(n_requests, rate=rate, seed=seed, n_runs=64)
+    if burst:
+        for q in reqs:
+            q.arrival = 0.0
+    srv = serve.Server(serve.PlainBackend("fp64"), hbm_budget=int(budget_gb * (1 << 30)), max_batch=1)
+    for r, w in runs.items():
+        if counts[r]:
+            srv.register_run(r, w, counts[r], initial=serve.initial_inputs(w, 1000 + r))
+    summ = srv.run_trace(reqs, progress=lambda d, n: log(f"plain fp64: {d}/{n} done"))
+    return dict(summ, peak_hbm_GB=srv.peak_used / (1 << 30))
+
+
+def bench_serve(rate, n_requests, seed, budget_gb, log, schedules=None, sweep=(), mix_rate=None,
+                matched_requests=10000, capacity_requests=300):
+    """Open-loop Poisson traces through the continuous-batching server (FP32 propagation, FP64
+    reductions): at `rate`, at further loads (fractions of `mix_rate`), and, against the plain
+    FP64 per-request path, at a load that path sustains: 0.7 x its capacity (measured closed
+    loop on `capacity_requests` requests), both on the same `matched_requests`-request trace."""
     out = {"rate_rps": rate, "requests": n_requests, "runs": 64, "objective_only": 0.1,
            "hbm_budget_GB": budget_gb, "backward_schedules": dict(schedules or {})}
     summ = serve_trace(rate, n_requests, seed, budget_gb, log, schedules)
@@ -180,84 +286,34 @@ def bench_serve(rate, n_requests, plain_requests, seed, budget_gb, log, schedule
                                       "p50_ms": sm["p50_ms"], "p99_ms": sm["p99_ms"], "mean_batch": sm["mean_batch"]})
             log(f"serve fp32 at {f:.2f} x mix rate: {sm['throughput_rps']:.1f} req/s p50 {sm['p50_ms']:.2f} ms "
                 f"p99 {sm['p99_ms']:.2f} ms")
-    if plain_requests > 0:
-        runs, reqs, counts = serve.make_trace(n_requests, rate=rate, seed=seed, n_runs=64)
-        reqs = reqs[:plain_requests]
-        cnt = {r: 0 for r in runs}
-        for q in reqs:
-            cnt[q.run_id] += 1
-        srv = serve.Server(serve.PlainBackend("fp64"), hbm_budget=int(budget_gb * (1 << 30)), max_batch=1)
-        for r, w in runs.items():
-            if cnt[r]:
-                srv.register_run(r, w, cnt[r], initial=serve.initial_inputs(w, 1000 + r))
-        summ = srv.run_trace(reqs, progress=lambda d, n: log(f"plain fp64: {d}/{n} done"))
-        out["plain_fp64_per_request"] = dict(summ, note=f"first {plain_requests} requests of the same trace")
-        log(f"serve plain fp64: {summ['throughput_rps']:.1f} req/s p50 {summ['p50_ms']:.2f} ms "
-            f"p99 {summ['p99_ms']:.2f} ms")
-    return out
-
-
-# The paper's optimisation results (Sec. 5, optimisation-results table): runtime to the stopping
-# rule on its CPU cluster, single-window reference and best multiple-shooting case.
-PAPER_OPT_SECONDS = {("QFT-4", 1): 2.3, ("QFT-4", 16): 0.5, ("QFT-8", 1): 145.0, ("QFT-8", 32): 23.0,
-                     ("QFT-16", 1): 59 * 60.0, ("QFT-16", 64): 12 * 60.0}
-
-
-def bench_optimize(runs, seed, log, time_limit, sigma=0.1):
-    """The quadratic-penalty L-BFGS driver (Sec. 3 with the Sec. 5 settings) on the paper's QFT
-    systems (2 levels, dipole chain, table durations and step counts), from the roll-out of a
-    random start in [-10, 10] MHz: wall time and iterations until the roll-out-infidelity estimate
-    falls below 1e-3 (the paper's stopping rule), also the first passes below 1e-1 and 1e-2
-    (checked every 50 iterations, every 10 for one window).  `runs`: [(qubits, windows, cap)]."""
-    import torch
-    from paper_2407_13950_amd import qoc, workloads as WL
-    out = {}
-    for q, M, cap in runs:
-        w = WL.paper_qft(q, M)
-        s = qoc.System(w, precision="fp32")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        opt = qoc.Optimizer(s, WL.gen_alpha(w, seed), None, sigma=sigma)
-        st0 = opt.run(0)
-        marks = {}
-        st = st0
-        chunk = 50 if M > 1 else 10
-        while st["stop"] == 0 and st["iterations"] < cap and time.perf_counter() - t0 < time_limit:
-            st = opt.run(min(chunk, cap - st["iterations"]))
-            el = time.perf_counter() - t0
-            for thr in (1e-1, 1e-2, 1e-3):
-                if st["estimate"] < thr and str(thr) not in marks:
-                    marks[str(thr)] = {"iterations": st["iterations"], "seconds": el}
-        el = time.perf_counter() - t0
-        its = max(st["iterations"], 1)
-        key = f"{w.name} M={M}" + (f" sigma={sigma}" if sigma != 0.1 else "")
-        out[key] = {"workload": f"{w.name}: q={w.q} L={w.L} T={w.T} ns N_T={w.n_steps} M={M} d={w.d} "
-                                f"variables={w.d + 2 * w.n_w}",
-                    "converged": st["stop_reason"] == "estimate", "seconds": el, "iterations": st["iterations"],
-                    "evaluations": st["evaluations"], "ms_per_iteration": 1e3 * el / its, "cap": cap,
-                    "stop": st["stop_reason"], "estimate": [st0["estimate"], st["estimate"]],
-                    "J": [st0["J"], st["J"]], "penalty": st["penalty"], "estimate_below": marks,
-                    "paper_seconds": PAPER_OPT_SECONDS.get((w.name, M))}
-        log(f"optimise {key}: {st['iterations']} iterations in {el:.2f} s ({st['stop_reason']}), estimate "
-            f"{st0['estimate']:.3e} -> {st['estimate']:.3e}, J {st['J']:.3e}")
-        opt.close()
-        s.close()
+    if matched_requests > 0:
+        cap = plain_trace(1.0, capacity_requests, seed + 1, budget_gb, log, burst=True)
+        capacity = cap["throughput_rps"]
+        r_m = 0.7 * capacity
+        log(f"plain fp64 capacity {capacity:.1f} req/s (closed loop, {capacity_requests} requests); "
+            f"matched load {r_m:.1f} req/s")
+        plain = plain_trace(r_m, matched_requests, seed, budget_gb, log)
+        batched = serve_trace(r_m, matched_requests, seed, budget_gb, log, schedules)
+        out["matched_load"] = {"rate_rps": r_m, "requests": matched_requests,
+                               "plain_fp64_capacity_rps": capacity,
+                               "plain_fp64_per_request": plain, "batched_fp32": batched,
+                               "note": "both paths on the same open-loop trace at 0.7 x the plain path's capacity"}
+        log(f"matched load {r_m:.1f} req/s: plain fp64 {plain['throughput_rps']:.1f} req/s p50 "
+            f"{plain['p50_ms']:.2f} ms p99 {plain['p99_ms']:.2f} ms; batched fp32 {batched['throughput_rps']:.1f} "
+            f"req/s p50 {batched['p50_ms']:.2f} ms p99 {batched['p99_ms']:.2f} ms")
     return out
 
 
 def bench_dipole(steps, warmup, seed, log):
-    """Evaluations with the dipole-coupled drift: the 4-qubit system with a 5 MHz exchange chain
-    added (same sizes as the headline), and the paper's QFT-16 system at M = 1, 64 and 256 (the
-    paper's gradient-speedup experiment: one gradient with M windows against M = 1).  Inputs
-    resident in HBM; returns evals/s, phases and the backward kernel's roofline fraction."""
+    """Evaluations with the dipole-coupled drift (eq. sys-ham's exchange chain): the 4-qubit
+    system with a 5 MHz chain added, at the headline sizes.  Inputs resident in HBM; returns
+    evals/s, phases and the backward kernel's roofline fraction."""
     import numpy as np
     import torch
     from paper_2407_13950_amd import qoc, workloads as WL
     out = {}
     c3 = WL.c3()
-    cases = (("4-qubit + dipole", c3.replace(dipole=np.full(3, 2 * math.pi * 5e-3), name="C3-q4L4-J")),
-             ("QFT-16 M=64", WL.paper_qft(4, 64)), ("QFT-16 M=256", WL.paper_qft(4, 256)),
-             ("QFT-16 M=1", WL.paper_qft(4, 1)))
+    cases = (("4-qubit + dipole", c3.replace(dipole=np.full(3, 2 * math.pi * 5e-3), name="C3-q4L4-J")),)
     for name, w in cases:
         nst = steps if w.n_windows > 1 else 2              # one window: a 0.3 s serial chain per evaluation
         s = qoc.System(w, precision="fp32")
@@ -294,11 +350,49 @@ def bench_dipole(steps, warmup, seed, log):
         log(f"dipole {name}: {nst / el:.1f} evals/s, backward {tm['backward']:.3f} ms, "
             f"{ach:.1f} TFLOP/s, count {tm['fixed_point_iters']}")
         s.close()
-    one = out.get("QFT-16 M=1", {}).get("value")
-    for M in (64, 256):
-        k = f"QFT-16 M={M}"
-        if one and k in out:
-            out[k]["speedup_vs_one_window"] = out[k]["value"] / one
+    return out
+
+
+def bench_small(w, precisions, steps, seed, log):
+    """One configured system evaluated on its own: evaluations/s and window-steps/s (2 N_T per
+    objective+gradient evaluation) per propagation precision, inputs and outputs resident in HBM.
+    Window states as configured (the GPU roll-out + noise, or QR-orthonormal states)."""
+    import torch
+    from paper_2407_13950_amd import qoc, workloads as WL
+    out = {"workload": f"{w.name}: q={w.q} L={w.L} N={w.N} E={w.E} N_T={w.n_steps} M={w.n_windows} d={w.d}"}
+    alpha = torch.tensor(WL.gen_alpha(w, seed), device="cuda")
+    W = None
+    for prec in precisions:
+        s = qoc.System(w, precision=prec)
+        s.set_controls(alpha)
+        if W is None:
+            if w.window_states == "qr":
+                W = torch.tensor(WL.gen_qr_states(w, seed), device="cuda")
+            else:
+                Wr, _ = s.rollout(device=True)
+                W = (Wr + torch.tensor(WL.gen_noise(w, seed), device="cuda")).contiguous()
+        s.set_window_states(W)
+        P = torch.empty(1, dtype=torch.float64, device="cuda")
+        terms = torch.empty(4 + w.n_windows, dtype=torch.float64, device="cuda")
+        ga = torch.empty(w.d, dtype=torch.float64, device="cuda")
+        gW = torch.empty((w.n_windows - 1, w.E, w.N), dtype=torch.complex128, device="cuda")
+        for _ in range(5):
+            s.gradient_into(P, terms, ga, gW)
+        torch.cuda.synchronize()
+        s.synchronize()
+        s.enable_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.gradient_into(P, terms, ga, gW)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        tm = s.timings()
+        s.synchronize()
+        out[prec] = {"value": steps / el, "unit": "evals/s", "window_steps_per_s": steps * 2 * w.n_steps / el,
+                     "ms_per_eval": 1e3 * el / steps, "steps": steps, "fixed_point_iters": tm["fixed_point_iters"],
+                     "backward_schedule": s.schedule(), "phases_ms": {k: tm[k] for k in qoc.PHASES}}
+        log(f"{w.name} {prec}: {steps / el:.1f} evals/s ({1e3 * el / steps:.3f} ms per evaluation)")
+        s.close()
     return out
 
 
@@ -341,26 +435,24 @@ def main():
     ap.add_argument("--warmup", type=int, default=15)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=3, help="steps of the plain FP64 form timed for comparison")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU-oracle sample size (0: skip)")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the CPU-oracle leg (the CPU baseline and the errors against the oracle)")
     ap.add_argument("--seed", type=int, default=2024)
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched-mix, serving, dipole and optimisation measurements")
-    ap.add_argument("--extras", default="dense,batch,serve,dipole,opt",
-                    help="which extra measurements to run (comma-separated subset of dense,batch,serve,dipole,opt)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 2/3-qubit configurations, batched mix, serving and dipole measurements")
+    ap.add_argument("--extras", default="small,dense,batch,serve,dipole",
+                    help="which extra measurements to run (comma-separated subset of small,dense,batch,serve,dipole)")
+    ap.add_argument("--small-steps", type=int, default=20, help="timed evaluations of the 2- and 3-qubit systems")
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--serve-requests", type=int, default=10000)
-    ap.add_argument("--serve-plain-requests", type=int, default=600)
+    ap.add_argument("--serve-matched-requests", type=int, default=10000,
+                    help="requests of the trace that both the plain FP64 path and the server run at 0.7 x the "
+                         "plain path's capacity (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="arrival rate as a fraction of the batched mix rate under the default schedule rule")
     ap.add_argument("--hbm-budget-gb", type=float, default=6.0)
     ap.add_argument("--serve-sweep", default="",
                     help="further serving loads (fractions of the mix rate, comma-separated) run after the main trace")
-    ap.add_argument("--opt-runs", default="2:16:3000,2:1:500,3:32:6000,3:1:400",
-                    help="optimisation runs on the paper's QFT systems, qubits:windows:iteration-cap, "
-                         "comma-separated (empty: skip); e.g. add 4:16:10000 for QFT-16 (~3 min)")
-    ap.add_argument("--opt-seconds", type=float, default=60.0, help="wall-time limit per optimisation run")
-    ap.add_argument("--opt-sigma", default="0.05",
-                    help="window-state scale(s) sigma of the optimisation runs, comma-separated (Sec. 5 scans "
-                         "0.05..0.15 per case; 0.05 needed the fewest iterations on every QFT case)")
     ap.add_argument("--dipole-steps", type=int, default=10, help="timed steps of the dipole systems (0: skip)")
     ap.add_argument("--windows", type=int, default=0,
                     help="window count of the 4-qubit system (0: its configured 128; other values change the "
@@ -397,7 +489,8 @@ def main():
     schedule = s.schedule()
     t0 = time.perf_counter()
     Wt, _ = s.rollout(device=True)
-    noise = torch.tensor(WL.gen_noise(w, args.seed), device=dev)
+    noise_np = WL.gen_noise(w, args.seed)
+    noise = torch.tensor(noise_np, device=dev)
     W = (Wt + noise).contiguous()
     s.set_window_states(W)
     torch.cuda.synchronize()
@@ -493,6 +586,13 @@ def main():
         log(f"fp64 plain form: {args.fp64_steps / e64:.2f} evals/s")
 
     extras = set() if args.no_extras else {e for e in args.extras.split(",") if e}
+    if "small" in extras:
+        try:
+            result["c1"] = bench_small(WL.c1(), ("fp64",), args.small_steps, args.seed, log)
+            result["c2"] = bench_small(WL.c2(), ("fp64", "fp32"), args.small_steps, args.seed, log)
+        except Exception as e:
+            result["small_error"] = repr(e)
+            log(f"2/3-qubit configurations failed: {e!r}")
     if "dense" in extras:
         try:
             result["dense_apply_check"] = dense_apply_check(w, kit, tm["forward"], log)
@@ -507,9 +607,9 @@ def main():
                 # rate under that rule
                 mix_rate = 64e3 / result["batched_mix"]["schedule"]["default_rule_ms"]
                 sweep = [float(x) for x in args.serve_sweep.split(",") if x]
-                result["serving"] = bench_serve(args.serve_load * mix_rate, args.serve_requests,
-                                                args.serve_plain_requests, args.seed, args.hbm_budget_gb, log,
-                                                sweep=sweep, mix_rate=mix_rate)
+                result["serving"] = bench_serve(args.serve_load * mix_rate, args.serve_requests, args.seed,
+                                                args.hbm_budget_gb, log, sweep=sweep, mix_rate=mix_rate,
+                                                matched_requests=args.serve_matched_requests)
         except Exception as e:   # the headline line must still be printed
             result["extras_error"] = repr(e)
             log(f"extras failed: {e!r}")
@@ -519,19 +619,18 @@ def main():
         except Exception as e:
             result["dipole_error"] = repr(e)
             log(f"dipole systems failed: {e!r}")
-    runs = [tuple(int(x) for x in r.split(":")) for r in args.opt_runs.split(",") if r]
-    if "opt" in extras and runs:
-        try:
-            result["optimisation"] = {}
-            for sg in (float(x) for x in args.opt_sigma.split(",")):
-                result["optimisation"].update(bench_optimize(runs, args.seed, log, args.opt_seconds, sg))
-        except Exception as e:
-            result["optimisation_error"] = repr(e)
-            log(f"optimisation failed: {e!r}")
 
-    if args.cpu_seconds > 0:
-        result["cpu_baseline"] = cpu_baseline(w, alpha_np, args.cpu_seconds)
-        log(f"cpu baseline: {result['cpu_baseline']['value']:.4f} evals/s")
+    if not args.no_cpu and w.n_windows == WL.c3().n_windows:
+        base, errors = cpu_baseline_and_errors(w, alpha_np, noise_np, schedule, log)
+        result["cpu_baseline"] = base
+        result["error_vs_oracle"] = dict(errors, note="each GPU form evaluated at the oracle's own inputs (roll-out "
+                                                      "+ the bench's noise for the 2- and 4-qubit systems, QR states "
+                                                      "for the 3-qubit one)")
+        for name in ("c1", "c2"):
+            if name in result:
+                result[name]["error_vs_oracle"] = {k.split("_", 1)[1]: v for k, v in errors.items()
+                                                   if k.startswith(name + "_")}
+        log(f"cpu baseline: {base['value']:.4f} evals/s on {base['cores']} threads ({base['cpu_model']})")
     print(json.dumps(result), flush=True)
 
 

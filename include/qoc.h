@@ -220,6 +220,26 @@ int qoc_batch_create(int32_t device, int32_t max_contexts, int64_t max_items, qo
 int qoc_batch_destroy(qoc_batch *b);
 int qoc_batch_run(qoc_batch *b, qoc_ctx *const *ctxs, int32_t n, const int32_t *want_grad, void *hip_stream);
 
+/* Per-context outcome of the last qoc_batch_run on b (the fixed-point bound check
+ * of Sec. 5's implicit solve, done per context as in qoc_objective): status[i] is
+ * QOC_OK or QOC_ENOTCONV for the i-th context of that run, so that one failed
+ * evaluation can be reported without failing the others.  qoc_batch_run moves each
+ * context's flag into the batch (a later qoc_synchronize on the context no longer
+ * reports it).  Waits for the run's work to complete.  n must equal the run's
+ * context count.  Valid until the next qoc_batch_run on b.  Errors: QOC_EINVAL
+ * (NULL, wrong n), QOC_ESTATE (b has not run). */
+int qoc_batch_status(qoc_batch *b, int32_t *status, int32_t n);
+
+/* The batched objective+gradient of n contexts in one call (Sec. 3.1 evaluated for
+ * many systems at once): a batch sized for these contexts runs them on the stream of
+ * ctxs[0] (every context's stream becomes that stream), as qoc_batch_run does, and the
+ * call waits for the work to finish.  want_grad (nullable: all) as in qoc_batch_run.
+ * Read each context's results with qoc_read_results.  Returns QOC_ENOTCONV when any
+ * context exceeded the fixed-point bound (the message lists them; the others' results
+ * are valid), and the errors of qoc_batch_create / qoc_batch_run.  Allocates and frees
+ * the batch's tables on every call: callers that evaluate repeatedly keep a qoc_batch. */
+int qoc_batch_gradient(qoc_ctx *const *ctxs, int32_t n, const int32_t *want_grad);
+
 /* Results of the last evaluation of ctx (single or batched) into caller buffers
  * (all nullable; layouts as in qoc_gradient; gradients only after a gradient
  * evaluation, else QOC_ESTATE).  Device outputs are copied on the context's

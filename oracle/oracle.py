@@ -78,6 +78,8 @@ def _load():
                 fn = getattr(lib, name)
                 fn.argtypes = args
                 fn.restype = ctypes.c_int
+            lib.orc_max_threads.argtypes = []
+            lib.orc_max_threads.restype = ctypes.c_int
             _lib = lib
     return _lib
 
@@ -254,3 +256,8 @@ def window_starts(w) -> np.ndarray:
     out = np.zeros(pb.M + 1, dtype=np.int64)
     _check(_load().orc_window_starts(pb.ref(), out.ctypes.data), "window_starts")
     return out
+
+
+def max_threads() -> int:
+    """OpenMP threads the oracle's (window, column) loops run on."""
+    return int(_load().orc_max_threads())

@@ -39,6 +39,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef double complex cplx;
 
@@ -269,7 +272,7 @@ static int forward_phase(const orc_sys *s, const double *alpha, const double *W,
     const int N = s->N, E = s->E;
     int status = ORC_OK;
     int ntask = (m1 - m0 + 1) * E;
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) reduction(min : status)
     for (int t = 0; t < ntask; ++t) {
         int m = m0 + t / E, c = t % E;
         cplx *u = malloc(sizeof(cplx) * 3 * N);
@@ -353,7 +356,7 @@ static int adjoint_phase(const orc_sys *s, const double *alpha, const double *W,
     const int d = 2 * p->d1 * p->q * p->nf;
     int status = ORC_OK;
     int ntask = (m1 - m0 + 1) * E;
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) reduction(min : status)
     for (int t = 0; t < ntask; ++t) {
         int m = m0 + t / E, c = t % E;
         long k0 = window_start(p, m), k1 = window_start(p, m + 1), nk = k1 - k0;
@@ -525,7 +528,7 @@ int orc_rollout(const orc_problem *p, const double *alpha, double *W_out, double
     if (rc) return rc;
     const int N = s.N, E = s.E, M = p->M;
     int status = ORC_OK;
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) reduction(min : status)
     for (int c = 0; c < E; ++c) {
         cplx *u = malloc(sizeof(cplx) * 3 * N);
         if (!u) { status = ORC_ENOMEM; continue; }
@@ -683,4 +686,14 @@ int orc_energy(const orc_problem *p, const double *alpha, double *E_out, double 
     }
     *E_out = dt * E;
     return ORC_OK;
+}
+
+/* Threads the parallel loops over (window, column) tasks use (1 without OpenMP). */
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

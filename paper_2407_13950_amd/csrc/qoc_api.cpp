@@ -528,6 +528,22 @@ int qoc_rollout(qoc_ctx *ctx, double *W_out, double *U_out, int32_t where) {
 
 // ---------------------------------------------------------------------------- batches
 
+// Sections of the pinned staging buffer of a batch: the systems, then the propagation items
+// (16-byte int4 records), then the small-kernel block table.  Each section starts on a 256-byte
+// boundary: the item records must be 16-byte aligned (their stores are 16-byte vector stores),
+// and sizeof(DevSys) times an odd context count is not a multiple of 16.
+struct StageLayout {
+  size_t items, blocks, total;
+};
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+static StageLayout stage_layout(int max_ctx, long long max_items, long long max_blocks) {
+  StageLayout l;
+  l.items = align256(sizeof(qoc::DevSys) * (size_t)max_ctx);
+  l.blocks = l.items + align256(sizeof(int4) * 2 * (size_t)max_items);
+  l.total = l.blocks + sizeof(int2) * (size_t)max_blocks;
+  return l;
+}
+
 struct qoc_batch {
   int device = 0;
   int max_ctx = 0;
@@ -543,15 +559,20 @@ struct qoc_batch {
   hipStream_t aux = nullptr;      // backward items of two wavefronts run here (default priority)
   hipStream_t aux2 = nullptr;     // backward items of three wavefronts run here (default priority)
   hipEvent_t fork = nullptr, join = nullptr, join2 = nullptr;
+  int *d_status = nullptr;        // [max_ctx] status words gathered at the end of a run
+  int *h_status = nullptr;        // pinned host copy of d_status
+  hipEvent_t done = nullptr;      // recorded after the status copy of the last run
+  int last_n = 0;                 // contexts of the last run (0: none yet)
   ~qoc_batch() {
+    if (done) { (void)hipEventSynchronize(done); (void)hipEventDestroy(done); }
     if (uploaded) { (void)hipEventSynchronize(uploaded); (void)hipEventDestroy(uploaded); }
     if (aux) { (void)hipStreamSynchronize(aux); (void)hipStreamDestroy(aux); }
     if (aux2) { (void)hipStreamSynchronize(aux2); (void)hipStreamDestroy(aux2); }
     if (fork) (void)hipEventDestroy(fork);
     if (join) (void)hipEventDestroy(join);
     if (join2) (void)hipEventDestroy(join2);
-    (void)hipFree(d_sys); (void)hipFree(d_items); (void)hipFree(d_blocks);
-    (void)hipHostFree(h_stage);
+    (void)hipFree(d_sys); (void)hipFree(d_items); (void)hipFree(d_blocks); (void)hipFree(d_status);
+    (void)hipHostFree(h_stage); (void)hipHostFree(h_status);
   }
 };
 
@@ -564,7 +585,7 @@ int qoc_batch_create(int32_t device, int32_t max_contexts, int64_t max_items, qo
   b->max_ctx = max_contexts;
   b->max_items = max_items;
   b->max_blocks = 4 * max_items + 1024LL * max_contexts;   // generous: small kernels need few blocks per system
-  b->stage_bytes = sizeof(qoc::DevSys) * max_contexts + sizeof(int4) * 2 * max_items + sizeof(int2) * b->max_blocks;
+  b->stage_bytes = stage_layout(max_contexts, max_items, b->max_blocks).total;
   hipError_t e = hipMalloc(&b->d_sys, sizeof(qoc::DevSys) * max_contexts);
   if (e == hipSuccess) e = hipMalloc(&b->d_items, sizeof(int4) * 2 * max_items);
   if (e == hipSuccess) e = hipMalloc(&b->d_blocks, sizeof(int2) * b->max_blocks);
@@ -575,6 +596,9 @@ int qoc_batch_create(int32_t device, int32_t max_contexts, int64_t max_items, qo
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->aux2, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join2, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipMalloc(&b->d_status, sizeof(int) * max_contexts);
+  if (e == hipSuccess) e = hipHostMalloc(&b->h_status, sizeof(int) * max_contexts, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
   if (e != hipSuccess) { delete b; return fail(QOC_ENOMEM, std::string("qoc_batch_create: ") + hipGetErrorString(e)); }
   *out = b;
   return QOC_OK;
@@ -639,9 +663,10 @@ int qoc_batch_run(qoc_batch *b, qoc_ctx *const *ctxs, int32_t n, const int32_t *
   // the previous run's uploads must have left the staging buffer
   if (b->pending) HIP_OR_RETURN(hipEventSynchronize(b->uploaded));
   char *h = b->h_stage;
+  const StageLayout lay = stage_layout(b->max_ctx, b->max_items, b->max_blocks);
   qoc::DevSys *hs = reinterpret_cast<qoc::DevSys *>(h);
-  int4 *hi = reinterpret_cast<int4 *>(h + sizeof(qoc::DevSys) * b->max_ctx);
-  int2 *hb = reinterpret_cast<int2 *>(h + sizeof(qoc::DevSys) * b->max_ctx + sizeof(int4) * 2 * b->max_items);
+  int4 *hi = reinterpret_cast<int4 *>(h + lay.items);
+  int2 *hb = reinterpret_cast<int2 *>(h + lay.blocks);
   for (int i = 0; i < n; ++i) hs[i] = ctxs[i]->dev;
   for (size_t k = 0; k < fwd.size(); ++k) hi[k] = fwd[k].v;
   for (size_t k = 0; k < bwd.size(); ++k) hi[fwd.size() + k] = bwd[k].v;
@@ -692,12 +717,63 @@ int qoc_batch_run(qoc_batch *b, qoc_ctx *const *ctxs, int32_t n, const int32_t *
       return hip_fail((hipError_t)e, "batched kernel launch");
     }
   }
+  // each context's status word moves into the batch's list (read by qoc_batch_status)
+  {
+    const int e = qoc::launch_gather_status(b->d_sys, n, b->d_status, st);
+    if (e) return hip_fail((hipError_t)e, "qoc_batch_run: status gather");
+  }
+  HIP_OR_RETURN(hipMemcpyAsync(b->h_status, b->d_status, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+  HIP_OR_RETURN(hipEventRecord(b->done, st));
+  b->last_n = n;
   for (int i = 0; i < n; ++i) {
     qoc_ctx *c = ctxs[i];
     c->stream = st;
     c->forward_valid = true;
     c->grad_valid = !want_grad || want_grad[i];
   }
+  return QOC_OK;
+}
+
+int qoc_batch_status(qoc_batch *b, int32_t *status, int32_t n) {
+  if (!b || !status) return fail(QOC_EINVAL, "qoc_batch_status: NULL argument");
+  if (b->last_n == 0) return fail(QOC_ESTATE, "qoc_batch_status: the batch has not run");
+  if (n != b->last_n)
+    return fail(QOC_EINVAL, "qoc_batch_status: the last run had " + std::to_string(b->last_n) + " contexts");
+  HIP_OR_RETURN(hipSetDevice(b->device));
+  HIP_OR_RETURN(hipEventSynchronize(b->done));
+  int bad = 0;
+  for (int i = 0; i < n; ++i) {
+    status[i] = (b->h_status[i] & qoc::STATUS_NOTCONV) ? QOC_ENOTCONV : QOC_OK;
+    bad += status[i] != QOC_OK;
+  }
+  if (bad) g_last_error = std::to_string(bad) + " of " + std::to_string(n) +
+                          " contexts exceeded the fixed-point contraction bound";
+  return QOC_OK;
+}
+
+int qoc_batch_gradient(qoc_ctx *const *ctxs, int32_t n, const int32_t *want_grad) {
+  if (!ctxs || n < 1) return fail(QOC_EINVAL, "qoc_batch_gradient: bad arguments");
+  long long nf = 0, nb = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i]) return fail(QOC_EINVAL, "qoc_batch_gradient: NULL context");
+    nf += (long long)ctxs[i]->M * ctxs[i]->dev.ncg;
+    nb += (long long)ctxs[i]->M * ctxs[i]->dev.ncg_b;
+  }
+  qoc_batch *b = nullptr;
+  int rc = qoc_batch_create(ctxs[0]->device, n, std::max(nf, nb), &b);
+  if (rc != QOC_OK) return rc;
+  hipStream_t st = ctxs[0]->stream;
+  rc = qoc_batch_run(b, ctxs, n, want_grad, st);
+  if (rc != QOC_OK) { qoc_batch_destroy(b); return rc; }
+  std::vector<int32_t> status(n);
+  rc = qoc_batch_status(b, status.data(), n);
+  qoc_batch_destroy(b);
+  if (rc != QOC_OK) return rc;
+  std::string bad;
+  for (int i = 0; i < n; ++i)
+    if (status[i] != QOC_OK) bad += (bad.empty() ? "" : ", ") + std::to_string(i);
+  if (!bad.empty())
+    return fail(QOC_ENOTCONV, "qoc_batch_gradient: contexts " + bad + " exceeded the fixed-point contraction bound");
   return QOC_OK;
 }
 

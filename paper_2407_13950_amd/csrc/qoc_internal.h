@@ -117,6 +117,8 @@ struct BatchPlan {
   int fp64;
 };
 int launch_batch_phase(const BatchPlan &p, int phase, hipStream_t st);
+// out[i] = status word of sys[i] (device copies), which is cleared; i < n.
+int launch_gather_status(const DevSys *sys, int n, int *out, hipStream_t st);
 
 // ---- optimisation driver (qoc_opt.cpp) and its FP64 kernels (qoc_opt_kernels.hip).
 // Reductions use kOptGrid partial sums (partials: >= kOptGrid doubles) finished by one

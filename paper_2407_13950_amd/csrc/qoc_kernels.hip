@@ -2354,7 +2354,22 @@ int batch_phase_T(const BatchPlan &p, int phase, hipStream_t st) {
   return (int)hipGetLastError();
 }
 
+// Status words of the systems of a batch, in batch order: out[i] = system i's flags,
+// which are then cleared (the batch reports them from here on).
+__global__ __launch_bounds__(256) void k_gather_status(const DevSys *sys, int n, int *out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  int *st = sys[i].status;
+  out[i] = st[0];
+  st[0] = 0;
+}
+
 }  // namespace
+
+int launch_gather_status(const DevSys *sys, int n, int *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_status, dim3((n + 255) / 256), dim3(256), 0, st, sys, n, out);
+  return (int)hipGetLastError();
+}
 
 int small_blocks(const DevSys &s, int kind) {
   switch (kind) {

@@ -36,7 +36,7 @@ EXPORTED = ["qoc_create", "qoc_destroy", "qoc_get_info", "qoc_set_stream", "qoc_
             "qoc_last_error", "qoc_strerror", "qoc_enable_timing", "qoc_get_timings", "qoc_backward",
             "qoc_batch_create", "qoc_batch_destroy", "qoc_batch_run", "qoc_read_results",
             "qoc_opt_create", "qoc_opt_destroy", "qoc_opt_run", "qoc_opt_get", "qoc_set_schedule",
-            "qoc_get_schedule"]
+            "qoc_get_schedule", "qoc_batch_status", "qoc_batch_gradient"]
 
 PHASES = ["controls", "forward", "boundary", "backward", "project", "grad_W", "total"]
 
@@ -88,10 +88,12 @@ _lib = None
 
 
 def load_library(path: str = LIB_PATH):
-    """Load libqoc.so (raises ImportError if it is missing)."""
+    """Load libqoc.so (raises ImportError if it is missing).  QOC_LIBRARY_OVERRIDE names another
+    build of the same library (e.g. one with sanitizers on its host code)."""
     global _lib
     if _lib is not None:
         return _lib
+    path = os.environ.get("QOC_LIBRARY_OVERRIDE") or path
     if not os.path.exists(path):
         raise ImportError(f"HIP library not built: {path} (run __graft_entry__.build())")
     lib = ctypes.CDLL(path)
@@ -122,6 +124,8 @@ def load_library(path: str = LIB_PATH):
         "qoc_opt_get": ([vp, vp, vp, i32], ctypes.c_int),
         "qoc_set_schedule": ([vp, i32], ctypes.c_int),
         "qoc_get_schedule": ([vp, ctypes.POINTER(i32)], ctypes.c_int),
+        "qoc_batch_status": ([vp, vp, i32], ctypes.c_int),
+        "qoc_batch_gradient": ([ctypes.POINTER(vp), i32, vp], ctypes.c_int),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -182,6 +186,9 @@ class System:
         _check(lib.qoc_get_info(self.h, ctypes.byref(inf)))
         self.info = {f: getattr(inf, f) for f, _ in Info._fields_}
         self.N, self.E, self.d, self.M = inf.N, inf.E, inf.d, inf.n_windows
+        # Bumped by every call that changes the inputs or re-runs the forward sweep; the
+        # autograd.Function compares it to detect that its forward state was replaced.
+        self.generation = 0
         if backward_schedule != "auto":
             self.set_schedule(backward_schedule)
 
@@ -207,11 +214,13 @@ class System:
     def set_controls(self, alpha):
         p, kind, keep = _ptr_and_kind(alpha, "f8")
         self._stream(kind == QOC_DEVICE)
+        self.generation += 1
         _check(_lib.qoc_set_controls(self.h, p, self.d, kind))
         self._alpha_keep = keep
 
     def set_window_states(self, W):
         n = 2 * (self.M - 1) * self.N * self.E
+        self.generation += 1
         if self.M == 1:
             _check(_lib.qoc_set_window_states(self.h, None, 0, QOC_HOST))
             return
@@ -241,6 +250,7 @@ class System:
         """Returns (P, terms)."""
         self._stream(device)
         out, ptr = self._outputs(device, grad=False)
+        self.generation += 1
         _check(_lib.qoc_objective(self.h, ptr["P"], ptr["terms"], QOC_DEVICE if device else QOC_HOST))
         return (out["P"] if device else float(out["P"][0])), out["terms"]
 
@@ -248,6 +258,7 @@ class System:
         """Returns (P, terms, grad_alpha, grad_W)."""
         self._stream(device)
         out, ptr = self._outputs(device, grad=True)
+        self.generation += 1
         _check(_lib.qoc_gradient(self.h, ptr["P"], ptr["terms"], ptr["grad_alpha"], ptr["grad_W"],
                                  QOC_DEVICE if device else QOC_HOST))
         P = out["P"] if device else float(out["P"][0])
@@ -256,6 +267,7 @@ class System:
     def gradient_into(self, P, terms, grad_alpha, grad_W):
         """Device-resident variant writing into caller tensors (no allocation, no sync)."""
         self._stream(True)
+        self.generation += 1
         _check(_lib.qoc_gradient(self.h, P.data_ptr(), terms.data_ptr() if terms is not None else None,
                                  grad_alpha.data_ptr(), grad_W.data_ptr() if grad_W is not None else None, QOC_DEVICE))
 
@@ -273,6 +285,7 @@ class System:
 
     def objective_into(self, P, terms):
         self._stream(True)
+        self.generation += 1
         _check(_lib.qoc_objective(self.h, P.data_ptr(), terms.data_ptr() if terms is not None else None, QOC_DEVICE))
 
     def rollout(self, device: bool = False):
@@ -364,7 +377,33 @@ class Batch:
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
+        for s in systems:
+            s.generation += 1
         _check(_lib.qoc_batch_run(self.h, arr, n, wg, ctypes.c_void_p(stream)))
+        self._n = n
+
+    def status(self):
+        """Per-system outcome of the last run (qoc_batch_status): QOC_OK or QOC_ENOTCONV each.
+        Waits for the run's work to finish."""
+        n = getattr(self, "_n", 0)
+        st = (ctypes.c_int32 * max(n, 1))()
+        _check(_lib.qoc_batch_status(self.h, ctypes.cast(st, ctypes.c_void_p), n))
+        return [int(x) for x in st[:n]]
+
+
+def batch_gradient(systems, want_grad=None):
+    """qoc_batch_gradient: evaluate all systems in one batched call and wait for it.  Raises
+    QocError(QOC_ENOTCONV) when a system exceeded the fixed-point bound (the others' results
+    stay valid; read them with read_results)."""
+    n = len(systems)
+    arr = (ctypes.c_void_p * n)(*[s.h.value for s in systems])
+    wg = None
+    if want_grad is not None:
+        keep = (ctypes.c_int32 * n)(*[1 if g else 0 for g in want_grad])
+        wg = ctypes.cast(keep, ctypes.c_void_p)
+    for s in systems:
+        s.generation += 1
+    _check(_lib.qoc_batch_gradient(arr, n, wg))
 
 
 STOP_REASONS = {0: "running", 1: "estimate", 2: "gradient", 3: "line search"}

@@ -49,6 +49,7 @@ class Request:
     done: float = math.nan
     result: Any = None
     inputs: Any = None
+    error: int = 0                       # nonzero: the evaluation failed (a QOC_E* code)
 
 
 @dataclasses.dataclass
@@ -212,7 +213,8 @@ class Server:
 
 def summarize(done: List[Request], wall: float) -> Dict[str, float]:
     lat = np.array([q.done - q.arrival for q in done])
-    return {"requests": len(done), "wall_s": wall, "throughput_rps": len(done) / wall if wall > 0 else math.nan,
+    return {"requests": len(done), "failed": sum(1 for q in done if q.error), "wall_s": wall,
+            "throughput_rps": len(done) / wall if wall > 0 else math.nan,
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "mean_ms": float(lat.mean() * 1e3)}
 
@@ -220,7 +222,15 @@ def summarize(done: List[Request], wall: float) -> Dict[str, float]:
 # ------------------------------------------------------------------- the HIP backend
 
 class QocBackend(Backend):
-    """Runs batches through the C ABI: one qoc_batch per stream, one qoc context per run."""
+    """Runs batches through the C ABI: one qoc_batch per stream, one qoc context per run.
+
+    A run holds, besides its context, its resident controls and window states and one
+    set of output buffers (P, terms, dP/dalpha, dP/dW) that every request of the run
+    reuses; all of it is in footprint().  The gradients stay on the device for the
+    run's next update; collect() copies each request's P and terms to the host (and,
+    with keep_results, its inputs and gradients), so completed requests hold no device
+    memory.  A request whose evaluation exceeded the fixed-point bound fails alone
+    (req.error = QOC_ENOTCONV, from qoc_batch_status); its gradient is not applied."""
 
     def __init__(self, precision: str = "fp32", n_streams: int = 4, max_batch: int = 64, max_items: int = 400000,
                  keep_results: bool = False, schedule: str = "auto",
@@ -246,24 +256,40 @@ class QocBackend(Backend):
         longest = -(-w.n_steps // w.n_windows)
         return int(math.log(max(longest * w.q, 1), 4))
 
+    @staticmethod
+    def resident_bytes(w) -> int:
+        """Device bytes a run holds beside its context: alpha and W, and the output buffers
+        P and terms (one buffer), dP/dalpha and dP/dW."""
+        n_w = 16 * (w.n_windows - 1) * w.N * w.E
+        return 2 * n_w + 2 * 8 * w.d + 8 * (5 + w.n_windows)
+
     def footprint(self, w) -> int:
-        key = (w.q, w.L, w.n_steps, w.n_windows, w.n_splines, w.n_carriers)
+        key = (w.q, w.L, w.n_steps, w.n_windows, w.n_splines, w.n_carriers, w.checkpoint_every)
         if key not in self._fp_cache:
             s = self.qoc.System(w, precision=self.precision)
             self._fp_cache[key] = s.info["device_bytes"]
             s.close()
-        n_w = 16 * (w.n_windows - 1) * w.N * w.E
-        return self._fp_cache[key] + 3 * n_w + 16 * w.d        # + resident W, grad_W and alpha copies
+        return self._fp_cache[key] + self.resident_bytes(w)
 
     def open(self, w, initial):
         torch = self.torch
         alpha0, W0 = initial
         s = self.qoc.System(w, precision=self.precision, backward_schedule=self.schedule)
         self.autotune.apply([s], self.schedules)
-        h = {"system": s, "w": w, "alpha": torch.as_tensor(alpha0, device="cuda").clone(),
-             "W": None, "g_alpha": None, "g_W": None}
+        f8, c16 = torch.float64, torch.complex128
+        # out: P and terms of the last evaluation, one buffer (5 + M doubles), and its pinned
+        # host copy, written on the batch's stream so that collect() needs no device call
+        h = {"system": s, "w": w, "alpha": torch.as_tensor(alpha0, dtype=f8, device="cuda").clone(), "W": None,
+             "out": torch.empty(5 + s.M, dtype=f8, device="cuda"),
+             "host": torch.empty(5 + s.M, dtype=f8, pin_memory=True),
+             "g_alpha": torch.empty(s.d, dtype=f8, device="cuda"), "g_W": None, "g_ok": False,
+             "ready": torch.cuda.Event()}
         if w.n_windows > 1:
-            h["W"] = torch.as_tensor(W0, device="cuda").clone().contiguous()
+            h["W"] = torch.as_tensor(W0, dtype=c16, device="cuda").clone().contiguous()
+            h["g_W"] = torch.empty((s.M - 1, s.E, s.N), dtype=c16, device="cuda")
+        # the copies above ran on the current stream; the run's first request waits for them
+        # on the device (launch()), so admission never blocks the host
+        h["ready"].record()
         return h
 
     def close(self, h):
@@ -273,55 +299,68 @@ class QocBackend(Backend):
     def _prepare(self, req, h):
         """Optimiser-style update of the resident inputs, then load them into the context."""
         s = h["system"]
-        if h["g_alpha"] is not None and req.lr_alpha:
+        if h["g_ok"] and req.lr_alpha:
             h["alpha"].sub_(req.lr_alpha * h["g_alpha"])
-        if h["W"] is not None and h["g_W"] is not None and req.lr_W:
+        if h["W"] is not None and h["g_ok"] and req.lr_W:
             h["W"].sub_(req.lr_W * h["g_W"])
         s.set_controls(h["alpha"])
         s.set_window_states(h["W"] if h["W"] is not None else None)
         if self.keep_results:
-            req.inputs = (h["alpha"].clone(), None if h["W"] is None else h["W"].clone())
+            req.inputs = (h["alpha"].cpu().numpy(), None if h["W"] is None else h["W"].cpu().numpy())
 
-    def _outputs(self, req, h):
-        torch = self.torch
-        s = h["system"]
-        out = {"P": torch.empty(1, dtype=torch.float64, device="cuda"),
-               "terms": torch.empty(4 + s.M, dtype=torch.float64, device="cuda"),
-               "grad_alpha": None, "grad_W": None}
-        if req.want_grad:
-            out["grad_alpha"] = torch.empty(s.d, dtype=torch.float64, device="cuda")
-            if s.M > 1:
-                out["grad_W"] = torch.empty((s.M - 1, s.E, s.N), dtype=torch.complex128, device="cuda")
-            h["g_alpha"], h["g_W"] = out["grad_alpha"], out["grad_W"]
-        return out
+    def _read(self, req, h):
+        """The evaluation's results into the run's output buffers and P, terms on to the pinned
+        host buffer, all on the current stream."""
+        h["system"].read_results_into(h["out"][:1], h["out"][1:], h["g_alpha"] if req.want_grad else None,
+                                      h["g_W"] if req.want_grad else None)
+        h["host"].copy_(h["out"], non_blocking=True)
 
     def launch(self, st, items, handles):
         torch = self.torch
         stream = self._streams[st]
         with torch.cuda.stream(stream):
             for req, h in zip(items, handles):
+                if h["ready"] is not None:          # first request of the run: its inputs' copies
+                    stream.wait_event(h["ready"])
+                    h["ready"] = None
                 self._prepare(req, h)
             self._batches[st].run([h["system"] for h in handles], [r.want_grad for r in items], stream.cuda_stream)
             for req, h in zip(items, handles):
-                out = self._outputs(req, h)
-                h["system"].read_results_into(out["P"], out["terms"], out["grad_alpha"], out["grad_W"])
-                req.result = out
+                self._read(req, h)
             ev = torch.cuda.Event()
             ev.record(stream)
-        return ev
+        return (ev, st)
 
     def ready(self, token) -> bool:
-        return token.query()
+        return token[0].query()
+
+    def _status(self, token, items, handles):
+        return self._batches[token[1]].status()
 
     def collect(self, token, items, handles):
-        token.synchronize()
+        token[0].synchronize()
+        status = self._status(token, items, handles)
+        ok = [(req, h) for req, h, code in zip(items, handles, status) if code == self.qoc.QOC_OK]
+        for req, h, code in zip(items, handles, status):
+            if code != self.qoc.QOC_OK:
+                req.error = code
+                req.result = None
+                h["g_ok"] = False       # the run's next update must not use this gradient
+        for req, h in ok:                   # copied on the batch's stream before its event
+            vals = h["host"].numpy()
+            req.result = {"P": float(vals[0]), "terms": vals[1:].copy()}
+            if req.want_grad:
+                h["g_ok"] = True
+                if self.keep_results:
+                    req.result["grad_alpha"] = h["g_alpha"].cpu().numpy()
+                    req.result["grad_W"] = None if h["g_W"] is None else h["g_W"].cpu().numpy()
 
 
 class PlainBackend(QocBackend):
     """The plain per-request path: one request at a time, single-context calls, FP64 by default."""
 
-    def __init__(self, precision: str = "fp64"):
-        super().__init__(precision=precision, n_streams=1, max_batch=1, max_items=1)
+    def __init__(self, precision: str = "fp64", keep_results: bool = False):
+        super().__init__(precision=precision, n_streams=1, max_batch=1, max_items=1, keep_results=keep_results)
 
     def launch(self, st, items, handles):
         torch = self.torch
@@ -329,17 +368,29 @@ class PlainBackend(QocBackend):
         req, h = items[0], handles[0]
         stream = self._streams[0]
         with torch.cuda.stream(stream):
+            if h["ready"] is not None:
+                stream.wait_event(h["ready"])
+                h["ready"] = None
             self._prepare(req, h)
-            out = self._outputs(req, h)
             s = h["system"]
             if req.want_grad:
-                s.gradient_into(out["P"], out["terms"], out["grad_alpha"], out["grad_W"])
+                s.gradient_into(h["out"][:1], h["out"][1:], h["g_alpha"], h["g_W"])
             else:
-                s.objective_into(out["P"], out["terms"])
-            req.result = out
+                s.objective_into(h["out"][:1], h["out"][1:])
+            h["host"].copy_(h["out"], non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(stream)
-        return ev
+        return (ev, st)
+
+    def _status(self, token, items, handles):
+        codes = []
+        for h in handles:               # the call's stream is idle: qoc_synchronize only reads the flag
+            try:
+                h["system"].synchronize()
+                codes.append(self.qoc.QOC_OK)
+            except self.qoc.QocError as e:
+                codes.append(e.code)
+        return codes
 
 
 # ------------------------------------------------------------------- synthetic trace

@@ -119,7 +119,13 @@ def test_c3_sampled_windows_match_oracle_pieces(c3_problem):
 
 
 def test_c3_central_differences_fp64():
-    """20 random unit directions over (alpha, Re W, Im W), h = 1e-6, on the FP64 path."""
+    """20 random unit directions over (alpha, Re W, Im W), h = 1e-6, on the FP64 path.
+
+    Error model of the central difference: truncation h^2/6 times the third directional
+    derivative (~1e-12 here) plus the rounding of the two objective values, a few ulps of P
+    each, divided by 2h.  The bound is 1e-6 |an| + 10 ulp(P)/(2h); for P ~ 1.1 the second term
+    is 1.1e-9.  Over ~1e6 variables a unit direction gives |an| ~ 1e-3 |grad|, so a purely
+    relative bound of 1e-7 would sit below the rounding floor for most directions."""
     w = WL.c3()
     alpha = WL.gen_alpha(w, 9)
     s = qoc.System(w, precision="fp64")
@@ -130,7 +136,7 @@ def test_c3_central_differences_fp64():
     P, terms, ga, gW = s.gradient()
     gnorm = np.linalg.norm(flat(ga, gW))
     h = 1e-6
-    worst = 0.0
+    floor = 10 * np.spacing(abs(P)) / (2 * h)
     rows = []
     for v in WL.gen_directions(w, 10, 20):
         s.set_controls(alpha + h * v["alpha"])
@@ -141,13 +147,12 @@ def test_c3_central_differences_fp64():
         Pm, _ = s.objective()
         fd = (Pp - Pm) / (2 * h)
         an = float(ga @ v["alpha"] + np.sum(gW.real * v["W"].real + gW.imag * v["W"].imag))
-        worst = max(worst, abs(fd - an) / (abs(an) + 1e-3 * gnorm))
         rows.append((abs(fd - an), abs(an)))
     rows = np.array(rows)
-    print(f"C3 FD worst scaled error {worst:.2e} (|grad| = {gnorm:.3e}, P = {P:.6f}); |fd - an| max "
-          f"{rows[:, 0].max():.2e}, median {np.median(rows[:, 0]):.2e}; |fd - an|/|an| max "
-          f"{(rows[:, 0] / rows[:, 1]).max():.2e}; |an| min {rows[:, 1].min():.2e}", flush=True)
-    assert worst <= 1e-5
+    print(f"C3 FD (|grad| = {gnorm:.3e}, P = {P:.6f}): |fd - an| max {rows[:, 0].max():.2e}, median "
+          f"{np.median(rows[:, 0]):.2e}; |fd - an|/|an| max {(rows[:, 0] / rows[:, 1]).max():.2e}; |an| min "
+          f"{rows[:, 1].min():.2e}; rounding floor {floor:.2e}", flush=True)
+    assert np.all(rows[:, 0] <= 1e-6 * rows[:, 1] + floor)
 
 
 def test_c3_autograd_function_matches_c_abi():

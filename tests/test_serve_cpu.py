@@ -148,3 +148,45 @@ def test_batches_hold_one_duration_class():
     for st, rids in be.log:
         assert len({runs[by_rid[i].run_id].q for i in rids}) == 1
     assert len(srv.completed) == 300
+
+
+class FailingBackend(FakeBackend):
+    """Evaluations of the runs in `bad` fail (as a fixed-point bound violation would)."""
+
+    def __init__(self, clock, bad, n_streams=2):
+        super().__init__(clock, n_streams)
+        self.bad = set(bad)
+
+    def collect(self, token, items, handles):
+        super().collect(token, items, handles)
+        for r in items:
+            if r.run_id in self.bad:
+                r.error = -4
+                r.result = None
+
+
+def test_failed_requests_do_not_block_others():
+    clock = FakeClock()
+    be = FailingBackend(clock, bad={2, 7})
+    runs = small_runs(12)
+    srv = serve.Server(be, hbm_budget=10 ** 12, max_batch=6, clock=clock)
+    _, reqs, counts = serve.make_trace(300, rate=20000.0, seed=8, n_runs=12)
+    for r, w in runs.items():
+        srv.register_run(r, w, counts[r])
+    summary = srv.run_trace(reqs)
+    assert summary["requests"] == 300
+    assert summary["failed"] == counts[2] + counts[7]
+    for q in srv.completed:
+        if q.run_id in (2, 7):
+            assert q.error and q.result is None
+        else:
+            assert q.error == 0 and q.result["ok"]
+    assert srv.used == 0 and not be.open_handles
+
+
+def test_qoc_backend_accounts_for_resident_buffers():
+    """The HIP backend's footprint covers the run's resident inputs and its reused output buffers
+    (alpha, W, P, terms, dP/dalpha, dP/dW) beside the context."""
+    w = WL.c3().replace(n_windows=16)
+    n_w = 16 * 15 * w.N * w.E
+    assert serve.QocBackend.resident_bytes(w) == 2 * n_w + 16 * w.d + 8 * (5 + 16)

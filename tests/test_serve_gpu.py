@@ -35,6 +35,7 @@ def test_served_results_equal_solo_results(schedule):
     assert max(srv.batch_sizes) > 1                      # requests were actually batched
     solo = {}
     for q in srv.completed:
+        assert q.error == 0
         w = runs[q.run_id]
         if q.run_id not in solo:
             solo[q.run_id] = qoc.System(w, precision="fp32", backward_schedule=schedule)
@@ -43,13 +44,48 @@ def test_served_results_equal_solo_results(schedule):
         s.set_controls(alpha)
         s.set_window_states(W if W is not None else None)
         if q.want_grad:
-            P, t, ga, gW = s.gradient(device=True)
-            assert torch.equal(P, q.result["P"]) and torch.equal(ga, q.result["grad_alpha"])
-            if gW is not None and q.result["grad_W"] is not None:
-                assert torch.equal(gW, q.result["grad_W"])
+            P, t, ga, gW = s.gradient()
+            assert P == q.result["P"] and np.array_equal(t, q.result["terms"])
+            assert np.array_equal(ga, q.result["grad_alpha"])
+            if q.result["grad_W"] is not None:
+                assert np.array_equal(gW, q.result["grad_W"])
         else:
-            P, t = s.objective(device=True)
-            assert torch.equal(P, q.result["P"]) and torch.equal(t, q.result["terms"])
+            P, t = s.objective()
+            assert P == q.result["P"] and np.array_equal(t, q.result["terms"])
+
+
+def test_unconverged_request_fails_alone():
+    """One run's controls are far too strong for its time step: the fixed-point bound check
+    flags its evaluations (qoc_batch_status), those requests fail with QOC_ENOTCONV, and every
+    other request of the same batches completes with the result of its solo evaluation."""
+    runs = small_runs(6, seed=3)
+    bad_run = 1
+    _, reqs, counts = serve.make_trace(60, rate=3000.0, seed=3, n_runs=6)
+    be = serve.QocBackend(precision="fp32", n_streams=2, max_batch=8, max_items=100000, keep_results=True)
+    srv = serve.Server(be, hbm_budget=8 << 30, max_batch=8)
+    for r, w in runs.items():
+        a0, W0 = serve.initial_inputs(w, 300 + r)
+        if r == bad_run:
+            a0 = a0 * 400.0
+        srv.register_run(r, w, counts[r], initial=(a0, W0))
+    summary = srv.run_trace(reqs)
+    assert summary["requests"] == 60 and summary["failed"] == counts[bad_run] > 0
+    assert max(srv.batch_sizes) > 1
+    mixed = 0
+    by_rid = {q.rid: q for q in srv.completed}
+    for q in srv.completed:
+        if q.run_id == bad_run:
+            assert q.error == qoc.QOC_ENOTCONV and q.result is None
+            continue
+        assert q.error == 0
+        s = qoc.System(runs[q.run_id], precision="fp32")
+        alpha, W = q.inputs
+        s.set_controls(alpha)
+        s.set_window_states(W if W is not None else None)
+        P, t = s.objective()
+        s.close()
+        assert P == q.result["P"] and np.array_equal(t, q.result["terms"])
+    print(summary, flush=True)
 
 
 def test_plain_fp64_path_serves_the_same_trace():
@@ -61,4 +97,4 @@ def test_plain_fp64_path_serves_the_same_trace():
     summary = srv.run_trace(reqs)
     assert summary["requests"] == 24 and max(srv.batch_sizes) == 1
     for q in srv.completed:
-        assert torch.isfinite(q.result["P"]).all()
+        assert q.error == 0 and np.isfinite(q.result["P"]) and np.all(np.isfinite(q.result["terms"]))
