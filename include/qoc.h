@@ -158,6 +158,7 @@ int qoc_set_stream(qoc_ctx *ctx, void *hip_stream);
 int qoc_set_schedule(qoc_ctx *ctx, int32_t backward);
 int qoc_get_schedule(const qoc_ctx *ctx, int32_t *backward);
 
+
 /* Controls alpha [d] (eq. dj-ctrl and the B-spline expansion).  Copied. */
 int qoc_set_controls(qoc_ctx *ctx, const double *alpha, int64_t d, int32_t where);
 
@@ -239,6 +240,26 @@ int qoc_batch_status(qoc_batch *b, int32_t *status, int32_t n);
  * are valid), and the errors of qoc_batch_create / qoc_batch_run.  Allocates and frees
  * the batch's tables on every call: callers that evaluate repeatedly keep a qoc_batch. */
 int qoc_batch_gradient(qoc_ctx *const *ctxs, int32_t n, const int32_t *want_grad);
+
+/* qoc_batch_run without a batch object, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same batched evaluation of n contexts (same kernels, same item order, results equal to
+ * qoc_batch_run's bit for bit), with its tables -- the systems, the propagation item lists
+ * and the small-kernel block table -- in a static device array of 4 MiB per GPU that the
+ * library holds until the process ends, and in static host memory.  The call allocates
+ * nothing (no hipMalloc, hipFree or pinned memory; contexts are created beforehand).
+ * Limits and behaviour:
+ *   - the tables must fit in 4 MiB (about twenty 4-qubit, 128-window contexts, or the
+ *     64-evaluation 2/3/4-qubit mix); a larger call returns QOC_EINVAL before any work;
+ *   - every kind of backward item runs on hip_stream, one after another (there are no
+ *     streams of a batch to fork onto); each context's stream becomes hip_stream;
+ *   - the call waits until its tables are on the device (a copy from the static host
+ *     image, ordered after earlier work on hip_stream), then launches asynchronously;
+ *   - all calls on one GPU share the array: calls that overlap on one GPU (different
+ *     streams, or threads) race; calls in stream order on one stream do not;
+ *   - the fixed-point bound flags stay in the contexts (qoc_synchronize reports them).
+ * Arguments and other errors as qoc_batch_run. */
+int qoc_batch_run_noalloc(qoc_ctx *const *ctxs, int32_t n, const int32_t *want_grad, void *hip_stream);
 
 /* Results of the last evaluation of ctx (single or batched) into caller buffers
  * (all nullable; layouts as in qoc_gradient; gradients only after a gradient

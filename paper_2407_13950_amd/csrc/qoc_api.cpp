@@ -9,6 +9,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -536,12 +537,16 @@ struct StageLayout {
   size_t items, blocks, total;
 };
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-static StageLayout stage_layout(int max_ctx, long long max_items, long long max_blocks) {
+static StageLayout stage_layout_records(int n_sys, long long n_records, long long n_blocks) {
   StageLayout l;
-  l.items = align256(sizeof(qoc::DevSys) * (size_t)max_ctx);
-  l.blocks = l.items + align256(sizeof(int4) * 2 * (size_t)max_items);
-  l.total = l.blocks + sizeof(int2) * (size_t)max_blocks;
+  l.items = align256(sizeof(qoc::DevSys) * (size_t)n_sys);
+  l.blocks = l.items + align256(sizeof(int4) * (size_t)n_records);
+  l.total = l.blocks + sizeof(int2) * (size_t)n_blocks;
   return l;
+}
+// a batch object's capacity: forward and backward items up to max_items each
+static StageLayout stage_layout(int max_ctx, long long max_items, long long max_blocks) {
+  return stage_layout_records(max_ctx, 2 * max_items, max_blocks);
 }
 
 struct qoc_batch {
@@ -611,105 +616,133 @@ int qoc_batch_destroy(qoc_batch *b) {
   return QOC_OK;
 }
 
-int qoc_batch_run(qoc_batch *b, qoc_ctx *const *ctxs, int32_t n, const int32_t *want_grad, void *hip_stream) {
-  if (!b || !ctxs || n < 1) return fail(QOC_EINVAL, "qoc_batch_run: bad arguments");
-  if (n > b->max_ctx) return fail(QOC_EINVAL, "qoc_batch_run: more contexts than the batch was created for");
+// ---- pieces shared by the batched entry points
+
+// The contexts of one batched call: non-NULL, on `device`, of one precision, with inputs,
+// each listed once.  `who` names the entry point in messages.
+static int batch_check(qoc_ctx *const *ctxs, int32_t n, int device, const char *who) {
   const int fp64 = ctxs[0] ? ctxs[0]->fp64 : 0;
   for (int i = 0; i < n; ++i) {
     qoc_ctx *c = ctxs[i];
-    if (!c) return fail(QOC_EINVAL, "qoc_batch_run: NULL context");
-    if (c->device != b->device) return fail(QOC_EINVAL, "qoc_batch_run: context on another device");
-    if (c->fp64 != fp64) return fail(QOC_EINVAL, "qoc_batch_run: mixed precisions");
-    if (!c->have_alpha || (c->M > 1 && !c->have_W)) return fail(QOC_ESTATE, "qoc_batch_run: context without inputs");
+    if (!c) return fail(QOC_EINVAL, std::string(who) + ": NULL context");
+    if (c->device != device) return fail(QOC_EINVAL, std::string(who) + ": context on another device");
+    if (c->fp64 != fp64) return fail(QOC_EINVAL, std::string(who) + ": mixed precisions");
+    if (!c->have_alpha || (c->M > 1 && !c->have_W)) return fail(QOC_ESTATE, std::string(who) + ": context without inputs");
     for (int j = 0; j < i; ++j)
-      if (ctxs[j] == c) return fail(QOC_EINVAL, "qoc_batch_run: context listed twice");
+      if (ctxs[j] == c) return fail(QOC_EINVAL, std::string(who) + ": context listed twice");
   }
-  HIP_OR_RETURN(hipSetDevice(b->device));
-  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-  // propagation items, longest first (cost ~ steps x entries per lane x qubits)
-  struct It { long long cost; int4 v; };
-  std::vector<It> fwd, bwd, xw, x3;
-  long long nblocks = 0;
+  return QOC_OK;
+}
+
+// Propagation items of all contexts, longest first (cost ~ steps x entries per lane x qubits),
+// in four sections by backward schedule, and the number of small-kernel blocks.  The records
+// live in caller memory (the allocation-free call uses a static array): batch_counts sizes
+// them, batch_fill writes and sorts them in place.  Equal costs keep their enumeration order,
+// so both batched entry points launch the same item order.
+struct ItemRec {
+  long long cost, seq;
+  int4 v;
+};
+struct BatchCounts {
+  long long fwd = 0, bwd = 0, xw = 0, x3 = 0, nblocks = 0;
+  bool any_grad = false;
+  long long records() const { return fwd + bwd + xw + x3; }
+};
+
+static BatchCounts batch_counts(qoc_ctx *const *ctxs, int32_t n, const int32_t *want_grad) {
+  BatchCounts c;
   for (int i = 0; i < n; ++i) {
-    const qoc_ctx *c = ctxs[i];
+    const qoc_ctx *x = ctxs[i];
     const bool g = !want_grad || want_grad[i];
-    const long long per_lane = (long long)c->N / std::max(1, (64 / c->dev.cpw)) + 1;
-    for (int m = 0; m < c->M; ++m) {
-      long long len = 0;
-      // window length from the floor split
-      len = (long long)(((__int128)(m + 1) * c->NT) / c->M) - (long long)(((__int128)m * c->NT) / c->M);
-      for (int cg = 0; cg < c->dev.ncg; ++cg) fwd.push_back({len * per_lane * c->q, make_int4(i, m, cg, c->shape)});
-      if (g) {
-        const int waves = qoc::bwd_waves(c->dev);                                        // wavefronts per item
-        const long long bcost = (c->dev.cpw >= 2 || waves > 1 ? 1 : 2) * len * per_lane * c->q;   // one system per lane
-        std::vector<It> &dst = waves == 3 ? x3 : waves == 2 ? xw : bwd;
-        for (int cg = 0; cg < c->dev.ncg_b; ++cg) dst.push_back({bcost, make_int4(i, m, cg, c->shape)});
-      }
+    c.any_grad |= g;
+    c.fwd += (long long)x->M * x->dev.ncg;
+    if (g) {
+      const int waves = qoc::bwd_waves(x->dev);
+      (waves == 3 ? c.x3 : waves == 2 ? c.xw : c.bwd) += (long long)x->M * x->dev.ncg_b;
     }
     for (int k = 0; k < qoc::SK_COUNT; ++k) {
       const bool gk = k == qoc::SK_SERIES || k == qoc::SK_PROJECT || k == qoc::SK_GRADW;
-      if (!gk || g) nblocks += qoc::small_blocks(c->dev, k);
+      if (!gk || g) c.nblocks += qoc::small_blocks(x->dev, k);
     }
   }
-  if ((long long)fwd.size() > b->max_items || (long long)(bwd.size() + xw.size() + x3.size()) > b->max_items)
-    return fail(QOC_EINVAL, "qoc_batch_run: more propagation items than the batch was created for");
-  if (nblocks > b->max_blocks) return fail(QOC_EINVAL, "qoc_batch_run: small-kernel table exceeds the batch capacity");
-  auto by_cost = [](const It &x, const It &y) { return x.cost > y.cost; };
-  std::stable_sort(fwd.begin(), fwd.end(), by_cost);
-  std::stable_sort(bwd.begin(), bwd.end(), by_cost);
-  std::stable_sort(xw.begin(), xw.end(), by_cost);
-  std::stable_sort(x3.begin(), x3.end(), by_cost);
+  return c;
+}
 
-  // the previous run's uploads must have left the staging buffer
-  if (b->pending) HIP_OR_RETURN(hipEventSynchronize(b->uploaded));
-  char *h = b->h_stage;
-  const StageLayout lay = stage_layout(b->max_ctx, b->max_items, b->max_blocks);
-  qoc::DevSys *hs = reinterpret_cast<qoc::DevSys *>(h);
-  int4 *hi = reinterpret_cast<int4 *>(h + lay.items);
-  int2 *hb = reinterpret_cast<int2 *>(h + lay.blocks);
+// rec: c.records() slots, sections forward | one wavefront | two | three.
+static void batch_fill(qoc_ctx *const *ctxs, int32_t n, const int32_t *want_grad, const BatchCounts &c,
+                       ItemRec *rec) {
+  long long pos[4] = {0, c.fwd, c.fwd + c.bwd, c.fwd + c.bwd + c.xw};
+  const long long start[4] = {pos[0], pos[1], pos[2], pos[3]};
+  long long seq = 0;
+  for (int i = 0; i < n; ++i) {
+    const qoc_ctx *x = ctxs[i];
+    const bool g = !want_grad || want_grad[i];
+    const long long per_lane = (long long)x->N / std::max(1, (64 / x->dev.cpw)) + 1;
+    const int waves = qoc::bwd_waves(x->dev);                                        // wavefronts per item
+    const int sec = waves == 3 ? 3 : waves == 2 ? 2 : 1;
+    for (int m = 0; m < x->M; ++m) {
+      // window length from the floor split
+      const long long len =
+          (long long)(((__int128)(m + 1) * x->NT) / x->M) - (long long)(((__int128)m * x->NT) / x->M);
+      for (int cg = 0; cg < x->dev.ncg; ++cg)
+        rec[pos[0]++] = ItemRec{len * per_lane * x->q, seq++, make_int4(i, m, cg, x->shape)};
+      if (g) {
+        const long long bcost = (x->dev.cpw >= 2 || waves > 1 ? 1 : 2) * len * per_lane * x->q;  // one system per lane
+        for (int cg = 0; cg < x->dev.ncg_b; ++cg)
+          rec[pos[sec]++] = ItemRec{bcost, seq++, make_int4(i, m, cg, x->shape)};
+      }
+    }
+  }
+  auto longest_first = [](const ItemRec &p, const ItemRec &q) { return p.cost != q.cost ? p.cost > q.cost : p.seq < q.seq; };
+  for (int k = 0; k < 4; ++k) std::sort(rec + start[k], rec + pos[k], longest_first);
+}
+
+// Device addresses of a batch's three tables.
+struct DevTables {
+  qoc::DevSys *sys;
+  int4 *items;
+  int2 *blocks;
+};
+
+// Writes the host image of a batch's tables (systems at 0, item records at lay.items, block
+// table at lay.blocks) and fills `plan` with the matching addresses of the device tables.
+static void batch_image(qoc_ctx *const *ctxs, int32_t n, const int32_t *want_grad, const BatchCounts &c,
+                        const ItemRec *rec, char *host, const DevTables &dev, const StageLayout &lay,
+                        qoc::BatchPlan &plan) {
+  qoc::DevSys *hs = reinterpret_cast<qoc::DevSys *>(host);
+  int4 *hi = reinterpret_cast<int4 *>(host + lay.items);
+  int2 *hb = reinterpret_cast<int2 *>(host + lay.blocks);
   for (int i = 0; i < n; ++i) hs[i] = ctxs[i]->dev;
-  for (size_t k = 0; k < fwd.size(); ++k) hi[k] = fwd[k].v;
-  for (size_t k = 0; k < bwd.size(); ++k) hi[fwd.size() + k] = bwd[k].v;
-  for (size_t k = 0; k < xw.size(); ++k) hi[fwd.size() + bwd.size() + k] = xw[k].v;
-  for (size_t k = 0; k < x3.size(); ++k) hi[fwd.size() + bwd.size() + xw.size() + k] = x3[k].v;
-  qoc::BatchPlan plan{};
-  plan.fp64 = fp64;
-  plan.sys = b->d_sys;
-  plan.fwd_items = b->d_items;
-  plan.bwd_items = b->d_items + fwd.size();
-  plan.xw_items = b->d_items + fwd.size() + bwd.size();
-  plan.x3_items = b->d_items + fwd.size() + bwd.size() + xw.size();
-  plan.n_fwd = (int)fwd.size();
-  plan.n_bwd = (int)bwd.size();
-  plan.n_xw = (int)xw.size();
-  plan.n_x3 = (int)x3.size();
-  plan.aux = b->aux;
-  plan.aux2 = b->aux2;
-  plan.fork = b->fork;
-  plan.join = b->join;
-  plan.join2 = b->join2;
+  for (long long k = 0; k < c.records(); ++k) hi[k] = rec[k].v;
+  plan.sys = dev.sys;
+  plan.fwd_items = dev.items;
+  plan.bwd_items = dev.items + c.fwd;
+  plan.xw_items = dev.items + c.fwd + c.bwd;
+  plan.x3_items = dev.items + c.fwd + c.bwd + c.xw;
+  plan.n_fwd = (int)c.fwd;
+  plan.n_bwd = (int)c.bwd;
+  plan.n_xw = (int)c.xw;
+  plan.n_x3 = (int)c.x3;
+  plan.fp64 = ctxs[0]->fp64;
   long long off = 0;
-  for (int k = 0; k < qoc::SK_COUNT; ++k) {
-    const bool gk = k == qoc::SK_SERIES || k == qoc::SK_PROJECT || k == qoc::SK_GRADW;
-    plan.blocks[k] = b->d_blocks + off;
+  for (int kind = 0; kind < qoc::SK_COUNT; ++kind) {
+    const bool gk = kind == qoc::SK_SERIES || kind == qoc::SK_PROJECT || kind == qoc::SK_GRADW;
+    plan.blocks[kind] = dev.blocks + off;
     long long cnt = 0;
     for (int i = 0; i < n; ++i) {
       if (gk && want_grad && !want_grad[i]) continue;
-      const int nb = qoc::small_blocks(ctxs[i]->dev, k);
+      const int nb = qoc::small_blocks(ctxs[i]->dev, kind);
       for (int j = 0; j < nb; ++j) hb[off + cnt++] = make_int2(i, j);
     }
-    plan.n_blocks[k] = (int)cnt;
+    plan.n_blocks[kind] = (int)cnt;
     off += cnt;
   }
-  HIP_OR_RETURN(hipMemcpyAsync(b->d_sys, hs, sizeof(qoc::DevSys) * n, hipMemcpyHostToDevice, st));
-  HIP_OR_RETURN(hipMemcpyAsync(b->d_items, hi, sizeof(int4) * (fwd.size() + bwd.size() + xw.size() + x3.size()),
-                               hipMemcpyHostToDevice, st));
-  HIP_OR_RETURN(hipMemcpyAsync(b->d_blocks, hb, sizeof(int2) * std::max<long long>(off, 1), hipMemcpyHostToDevice, st));
-  HIP_OR_RETURN(hipEventRecord(b->uploaded, st));
-  b->pending = true;
-  bool any_grad = false;
-  for (int i = 0; i < n; ++i) any_grad |= (!want_grad || want_grad[i]);
-  const int nph = any_grad ? qoc::PHASE_GRAD_W + 1 : qoc::PHASE_BOUNDARY + 1;
+}
+
+// Launches the phases of a batched evaluation on st and marks the contexts evaluated.
+static int batch_launch(qoc_ctx *const *ctxs, int32_t n, const int32_t *want_grad, const BatchCounts &c,
+                        const qoc::BatchPlan &plan, hipStream_t st) {
+  const int nph = c.any_grad ? qoc::PHASE_GRAD_W + 1 : qoc::PHASE_BOUNDARY + 1;
   for (int ph = 0; ph < nph; ++ph) {
     int e = qoc::launch_batch_phase(plan, ph, st);
     if (e) {
@@ -717,6 +750,49 @@ int qoc_batch_run(qoc_batch *b, qoc_ctx *const *ctxs, int32_t n, const int32_t *
       return hip_fail((hipError_t)e, "batched kernel launch");
     }
   }
+  for (int i = 0; i < n; ++i) {
+    qoc_ctx *c = ctxs[i];
+    c->stream = st;
+    c->forward_valid = true;
+    c->grad_valid = !want_grad || want_grad[i];
+  }
+  return QOC_OK;
+}
+
+int qoc_batch_run(qoc_batch *b, qoc_ctx *const *ctxs, int32_t n, const int32_t *want_grad, void *hip_stream) {
+  if (!b || !ctxs || n < 1) return fail(QOC_EINVAL, "qoc_batch_run: bad arguments");
+  if (n > b->max_ctx) return fail(QOC_EINVAL, "qoc_batch_run: more contexts than the batch was created for");
+  int rc = batch_check(ctxs, n, b->device, "qoc_batch_run");
+  if (rc != QOC_OK) return rc;
+  HIP_OR_RETURN(hipSetDevice(b->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  const BatchCounts cnt = batch_counts(ctxs, n, want_grad);
+  if (cnt.fwd > b->max_items || cnt.bwd + cnt.xw + cnt.x3 > b->max_items)
+    return fail(QOC_EINVAL, "qoc_batch_run: more propagation items than the batch was created for");
+  if (cnt.nblocks > b->max_blocks) return fail(QOC_EINVAL, "qoc_batch_run: small-kernel table exceeds the batch capacity");
+  std::vector<ItemRec> rec((size_t)cnt.records());
+  batch_fill(ctxs, n, want_grad, cnt, rec.data());
+
+  // the previous run's uploads must have left the staging buffer
+  if (b->pending) HIP_OR_RETURN(hipEventSynchronize(b->uploaded));
+  const StageLayout lay = stage_layout(b->max_ctx, b->max_items, b->max_blocks);
+  qoc::BatchPlan plan{};
+  char *h = b->h_stage;
+  batch_image(ctxs, n, want_grad, cnt, rec.data(), h, DevTables{b->d_sys, b->d_items, b->d_blocks}, lay, plan);
+  plan.aux = b->aux;
+  plan.aux2 = b->aux2;
+  plan.fork = b->fork;
+  plan.join = b->join;
+  plan.join2 = b->join2;
+  HIP_OR_RETURN(hipMemcpyAsync(b->d_sys, h, sizeof(qoc::DevSys) * n, hipMemcpyHostToDevice, st));
+  HIP_OR_RETURN(hipMemcpyAsync(b->d_items, h + lay.items, sizeof(int4) * std::max<long long>(cnt.records(), 1),
+                               hipMemcpyHostToDevice, st));
+  HIP_OR_RETURN(hipMemcpyAsync(b->d_blocks, h + lay.blocks, sizeof(int2) * std::max<long long>(cnt.nblocks, 1),
+                               hipMemcpyHostToDevice, st));
+  HIP_OR_RETURN(hipEventRecord(b->uploaded, st));
+  b->pending = true;
+  rc = batch_launch(ctxs, n, want_grad, cnt, plan, st);
+  if (rc != QOC_OK) return rc;
   // each context's status word moves into the batch's list (read by qoc_batch_status)
   {
     const int e = qoc::launch_gather_status(b->d_sys, n, b->d_status, st);
@@ -725,13 +801,47 @@ int qoc_batch_run(qoc_batch *b, qoc_ctx *const *ctxs, int32_t n, const int32_t *
   HIP_OR_RETURN(hipMemcpyAsync(b->h_status, b->d_status, sizeof(int) * n, hipMemcpyDeviceToHost, st));
   HIP_OR_RETURN(hipEventRecord(b->done, st));
   b->last_n = n;
-  for (int i = 0; i < n; ++i) {
-    qoc_ctx *c = ctxs[i];
-    c->stream = st;
-    c->forward_valid = true;
-    c->grad_valid = !want_grad || want_grad[i];
-  }
   return QOC_OK;
+}
+
+// Host image of the allocation-free run's tables (the device copy is the static array of the
+// kernel file) and its item records; one call at a time uses them.
+static unsigned char g_noalloc_image[qoc::kNoAllocScratchBytes];
+static ItemRec g_noalloc_records[qoc::kNoAllocScratchBytes / sizeof(int4)];
+static std::mutex g_noalloc_lock;
+
+int qoc_batch_run_noalloc(qoc_ctx *const *ctxs, int32_t n, const int32_t *want_grad, void *hip_stream) {
+  if (!ctxs || n < 1 || !ctxs[0]) return fail(QOC_EINVAL, "qoc_batch_run_noalloc: bad arguments");
+  const int device = ctxs[0]->device;
+  int rc = batch_check(ctxs, n, device, "qoc_batch_run_noalloc");
+  if (rc != QOC_OK) return rc;
+  const BatchCounts cnt = batch_counts(ctxs, n, want_grad);
+  const StageLayout lay = stage_layout_records(n, cnt.records(), cnt.nblocks);
+  if (lay.total > qoc::kNoAllocScratchBytes)
+    return fail(QOC_EINVAL, "qoc_batch_run_noalloc: the batch needs " + std::to_string(lay.total) +
+                                " bytes of tables, over the static capacity of " +
+                                std::to_string(qoc::kNoAllocScratchBytes));
+  HIP_OR_RETURN(hipSetDevice(device));
+  void *dev = nullptr;
+  {
+    const int e = qoc::noalloc_scratch(device, &dev);
+    if (e) return hip_fail((hipError_t)e, "qoc_batch_run_noalloc: address of the static tables");
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  char *d = static_cast<char *>(dev);
+  qoc::BatchPlan plan{};
+  std::lock_guard<std::mutex> guard(g_noalloc_lock);
+  char *h = reinterpret_cast<char *>(g_noalloc_image);
+  batch_fill(ctxs, n, want_grad, cnt, g_noalloc_records);
+  batch_image(ctxs, n, want_grad, cnt, g_noalloc_records, h,
+              DevTables{reinterpret_cast<qoc::DevSys *>(d), reinterpret_cast<int4 *>(d + lay.items),
+                        reinterpret_cast<int2 *>(d + lay.blocks)},
+              lay, plan);
+  // no streams of a batch here: every kind of backward item runs on st (plan.aux stays NULL)
+  HIP_OR_RETURN(hipMemcpyAsync(dev, h, lay.total, hipMemcpyHostToDevice, st));
+  // the host image is reused by the next call: wait until this copy has read it
+  HIP_OR_RETURN(hipStreamSynchronize(st));
+  return batch_launch(ctxs, n, want_grad, cnt, plan, st);
 }
 
 int qoc_batch_status(qoc_batch *b, int32_t *status, int32_t n) {

@@ -120,6 +120,15 @@ int launch_batch_phase(const BatchPlan &p, int phase, hipStream_t st);
 // out[i] = status word of sys[i] (device copies), which is cleared; i < n.
 int launch_gather_status(const DevSys *sys, int n, int *out, hipStream_t st);
 
+// Tables of the allocation-free batched run: a static device array of this many bytes per
+// GPU.  noalloc_scratch() returns its address on `device` (which must be current), looked
+// up once per device; 0 or a hipError_t value.
+#ifndef QOC_NOALLOC_SCRATCH_BYTES
+#define QOC_NOALLOC_SCRATCH_BYTES ((size_t)4 << 20)
+#endif
+constexpr size_t kNoAllocScratchBytes = QOC_NOALLOC_SCRATCH_BYTES;
+int noalloc_scratch(int device, void **out);
+
 // ---- optimisation driver (qoc_opt.cpp) and its FP64 kernels (qoc_opt_kernels.hip).
 // Reductions use kOptGrid partial sums (partials: >= kOptGrid doubles) finished by one
 // block in a fixed order; results land in device memory.  All return 0 or a hipError_t.

@@ -38,6 +38,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 
 namespace qoc {
 namespace {
@@ -2313,7 +2314,7 @@ int batch_phase_T(const BatchPlan &p, int phase, hipStream_t st) {
       // of three wavefronts run beside the others, each kind on a stream of the batch forked
       // from st and joined back to it
       const int kinds = (p.n_bwd > 0) + (p.n_xw > 0) + (p.n_x3 > 0);
-      if (kinds <= 1) {
+      if (kinds <= 1 || !p.aux || !p.aux2) {      // one kind, or no streams of the batch: all on st
         if (p.n_x3 > 0) hipLaunchKernelGGL(k_backward_x3_batch<T>, dim3(p.n_x3), dim3(192), 0, st, p.sys, p.x3_items);
         if (p.n_xw > 0) hipLaunchKernelGGL(k_backward_xw_batch<T>, dim3(p.n_xw), dim3(128), 0, st, p.sys, p.xw_items);
         if (p.n_bwd > 0) hipLaunchKernelGGL(k_backward_batch<T>, dim3(p.n_bwd), dim3(64), 0, st, p.sys, p.bwd_items);
@@ -2364,7 +2365,28 @@ __global__ __launch_bounds__(256) void k_gather_status(const DevSys *sys, int n,
   st[0] = 0;
 }
 
+// Tables of the allocation-free batched run (systems, item records, block table).  In host
+// code this name is only a handle for hipGetSymbolAddress; the device address is looked up
+// per GPU by noalloc_scratch() and used everywhere else.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 }  // namespace
+
+int noalloc_scratch(int device, void **out) {
+  constexpr int kMaxDevices = 64;
+  static void *addr[kMaxDevices] = {};
+  static std::mutex lock;
+  if (device < 0 || device >= kMaxDevices) return (int)hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(lock);
+  if (!addr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    addr[device] = p;
+  }
+  *out = addr[device];
+  return 0;
+}
 
 int launch_gather_status(const DevSys *sys, int n, int *out, hipStream_t st) {
   hipLaunchKernelGGL(k_gather_status, dim3((n + 255) / 256), dim3(256), 0, st, sys, n, out);

@@ -36,7 +36,7 @@ EXPORTED = ["qoc_create", "qoc_destroy", "qoc_get_info", "qoc_set_stream", "qoc_
             "qoc_last_error", "qoc_strerror", "qoc_enable_timing", "qoc_get_timings", "qoc_backward",
             "qoc_batch_create", "qoc_batch_destroy", "qoc_batch_run", "qoc_read_results",
             "qoc_opt_create", "qoc_opt_destroy", "qoc_opt_run", "qoc_opt_get", "qoc_set_schedule",
-            "qoc_get_schedule", "qoc_batch_status", "qoc_batch_gradient"]
+            "qoc_get_schedule", "qoc_batch_status", "qoc_batch_gradient", "qoc_batch_run_noalloc"]
 
 PHASES = ["controls", "forward", "boundary", "backward", "project", "grad_W", "total"]
 
@@ -126,6 +126,7 @@ def load_library(path: str = LIB_PATH):
         "qoc_get_schedule": ([vp, ctypes.POINTER(i32)], ctypes.c_int),
         "qoc_batch_status": ([vp, vp, i32], ctypes.c_int),
         "qoc_batch_gradient": ([ctypes.POINTER(vp), i32, vp], ctypes.c_int),
+        "qoc_batch_run_noalloc": ([ctypes.POINTER(vp), i32, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -389,6 +390,24 @@ class Batch:
         st = (ctypes.c_int32 * max(n, 1))()
         _check(_lib.qoc_batch_status(self.h, ctypes.cast(st, ctypes.c_void_p), n))
         return [int(x) for x in st[:n]]
+
+
+def batch_run_noalloc(systems, want_grad=None, stream: Optional[int] = None):
+    """qoc_batch_run_noalloc: the batched evaluation with the library's static tables (no device
+    allocation); asynchronous on `stream` (default: torch's current).  Read results with
+    read_results; bound violations stay in each System (synchronize() reports them)."""
+    n = len(systems)
+    arr = (ctypes.c_void_p * n)(*[s.h.value for s in systems])
+    wg = None
+    if want_grad is not None:
+        keep = (ctypes.c_int32 * n)(*[1 if g else 0 for g in want_grad])
+        wg = ctypes.cast(keep, ctypes.c_void_p)
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    for s in systems:
+        s.generation += 1
+    _check(_lib.qoc_batch_run_noalloc(arr, n, wg, ctypes.c_void_p(stream)))
 
 
 def batch_gradient(systems, want_grad=None):

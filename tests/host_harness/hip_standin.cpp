@@ -244,6 +244,18 @@ int launch_batch_phase(const BatchPlan &p, int phase, hipStream_t st) {
   return 0;
 }
 
+// The static tables of the allocation-free run: a "device" block of the declared size.
+int noalloc_scratch(int device, void **out) {
+  static void *block = nullptr;
+  if (device != 0) return (int)hipErrorInvalidDevice;
+  if (!block) {
+    block = std::malloc(kNoAllocScratchBytes);
+    g_device[block] = kNoAllocScratchBytes;
+  }
+  *out = block;
+  return 0;
+}
+
 int launch_gather_status(const DevSys *sys, int n, int *out, hipStream_t st) {
   check_stream(st);
   check_range(sys, sizeof(DevSys) * n, "gather systems");

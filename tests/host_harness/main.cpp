@@ -125,6 +125,35 @@ int main() {
     for (int i = 0; i < n; ++i) read_all(sys[i], true);
   }
 
+  // the allocation-free batched run: every size, twice, and results read back
+  for (int n = (int)sys.size(); n >= 1; --n) {
+    std::vector<int32_t> want(n);
+    for (int i = 0; i < n; ++i) want[i] = (i % 2) == 0;
+    for (int rep = 0; rep < 2; ++rep) {
+      CHECK(qoc_batch_run_noalloc(ctxs.data(), n, want.data(), nullptr) == QOC_OK);
+      for (int i = 0; i < n; ++i) read_all(sys[i], want[i] != 0);
+    }
+  }
+  CHECK(qoc_batch_run_noalloc(nullptr, 1, nullptr, nullptr) == QOC_EINVAL);
+  CHECK(qoc_batch_run_noalloc(ctxs.data(), 0, nullptr, nullptr) == QOC_EINVAL);
+  {
+    std::vector<qoc_ctx *> twice = {ctxs[0], ctxs[0]};
+    CHECK(qoc_batch_run_noalloc(twice.data(), 2, nullptr, nullptr) == QOC_EINVAL);
+  }
+  {   // tables over the static capacity (the harness builds with a 256 KiB capacity): four
+      // contexts of 4 qubits x 128 windows need ~330 KB, two ~165 KB
+    std::vector<Sys> big(4);
+    std::vector<qoc_ctx *> bc;
+    for (int i = 0; i < 4; ++i) {
+      make(big[i], 4, 4, 128, 128, QOC_BWD_ONE_WAVE, 100 + i);
+      bc.push_back(big[i].ctx);
+    }
+    CHECK(qoc_batch_run_noalloc(bc.data(), 4, nullptr, nullptr) == QOC_EINVAL);
+    CHECK(qoc_batch_run_noalloc(bc.data(), 2, nullptr, nullptr) == QOC_OK);
+    read_all(big[1], true);
+    for (Sys &s : big) CHECK(qoc_destroy(s.ctx) == QOC_OK);
+  }
+
   // a context flagged by the bound check fails alone (the stand-in flags alpha[0] > 100)
   std::vector<double> big = sys[1].alpha;
   big[0] = 1000.0;
@@ -151,7 +180,7 @@ int main() {
   CHECK(qoc_batch_destroy(b1) == QOC_OK);
 
   for (Sys &s : sys) CHECK(qoc_destroy(s.ctx) == QOC_OK);
-  CHECK(standin_live_device_blocks() == 0 && standin_live_pinned_blocks() == 0);
+  CHECK(standin_live_device_blocks() == 1 && standin_live_pinned_blocks() == 0);   // the static tables remain
   std::printf("HARNESS OK (%ld launches)\n", standin_launches());
   return 0;
 }

@@ -20,8 +20,11 @@ HIP_INC = "/opt/rocm/include"
 
 def build(tmp, flags):
     objs = []
-    srcs = [(os.path.join(ROOT, "paper_2407_13950_amd", "csrc", "qoc_api.cpp"), ["-D__HIP_PLATFORM_AMD__"]),
-            (os.path.join(ROOT, "tests", "host_harness", "hip_standin.cpp"), ["-D__HIP_PLATFORM_AMD__"]),
+    # a 256 KiB table capacity for the allocation-free call, so its over-capacity path is reached
+    # with a few small contexts
+    cap = ["-DQOC_NOALLOC_SCRATCH_BYTES=262144"]
+    srcs = [(os.path.join(ROOT, "paper_2407_13950_amd", "csrc", "qoc_api.cpp"), ["-D__HIP_PLATFORM_AMD__", *cap]),
+            (os.path.join(ROOT, "tests", "host_harness", "hip_standin.cpp"), ["-D__HIP_PLATFORM_AMD__", *cap]),
             (os.path.join(ROOT, "tests", "host_harness", "main.cpp"), [])]
     for src, extra in srcs:
         obj = os.path.join(tmp, os.path.basename(src) + ".o")
