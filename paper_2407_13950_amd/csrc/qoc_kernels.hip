@@ -434,6 +434,9 @@ __device__ __forceinline__ void lane_exchange(const Lane<T, Q, L, LD> &ln, const
     wave_sync();
     if constexpr (XPre<T>::value) {
       LaneGets<T, LD, K, 0>::load(ln, n);
+      // keep the caller's register-digit arithmetic after the reads' issue, where it covers
+      // their latency (left alone, the scheduler places it between the write and the reads)
+      __builtin_amdgcn_sched_barrier(0);
       wave_sync();
     }
   }
