@@ -277,7 +277,7 @@ int qoc_create(const qoc_system_desc *desc, qoc_ctx **out) {
   ALLOC(s.ckpt, sizeof(double) * 2 * nst * s.ncp);
   ALLOC(s.partials, sizeof(double) * 4 * M);
   ALLOC(s.scal, sizeof(double) * (5 + M));
-  ALLOC(s.series, sizeof(double) * (size_t)M * s.ncg_b * maxlen * 2 * q);
+  ALLOC(s.series, tsz * (size_t)M * s.ncg_b * maxlen * 2 * q);
   ALLOC(s.xy, sizeof(double) * (size_t)NT * 2 * q);
   ALLOC(s.grad_alpha, sizeof(double) * c->d);
   ALLOC(s.grad_W, sizeof(double) * 2 * (size_t)(M - 1) * E * N);

@@ -48,7 +48,8 @@ struct DevSys {
   double *ckpt;             // [2*M*ncp*E*N] complex checkpoints
   double *partials;         // [4*M]
   double *scal;             // [5+M]: P, J, penalty, |U^M|^2, Re gamma, Im gamma, |C^1|^2..|C^{M-1}|^2
-  double *series;           // [M*ncg*maxlen*2q]: per wavefront and step, Im<y,(a+a^+)z>, Re<y,(a-a^+)z>
+  double *series;           // [M*ncg*maxlen*2q] in the propagation precision: per wavefront and step,
+                            // Im<y,(a+a^+)z>, Re<y,(a-a^+)z>
   double *xy;               // [NT*2q]: the same summed over the window's columns
   double *grad_alpha;       // [d]
   double *grad_W;           // [2*(M-1)*E*N]

@@ -704,6 +704,13 @@ __device__ __forceinline__ void pair_terms(T yer, T yei, T zer, T zei, T yfr, T 
   a1 = fma_(-yei, zfr, a1); a1 = fma_(yfr, zei, a1); a1 = fma_(-yfi, zer, a1);
   a2 = fma_(yei, zfi, a2); a2 = fma_(-yfr, zer, a2); a2 = fma_(-yfi, zei, a2);
 }
+// The same terms added onto running sums a1, a2 (one chain each, no separate add).
+template <typename T>
+__device__ __forceinline__ void pair_terms_acc(T yer, T yei, T zer, T zei, T yfr, T yfi, T zfr, T zfi, T &a1,
+                                               T &a2) {
+  a1 = fma_(yer, zfi, a1); a1 = fma_(-yei, zfr, a1); a1 = fma_(yfr, zei, a1); a1 = fma_(-yfi, zer, a1);
+  a2 = fma_(yer, zfr, a2); a2 = fma_(yei, zfi, a2); a2 = fma_(-yfr, zer, a2); a2 = fma_(-yfi, zei, a2);
+}
 
 // ---------------------------------------------------------------------------- red-black half sweep
 
@@ -909,13 +916,10 @@ __device__ __forceinline__ void last_inner_lane(const Lane<T, Q, L, LD> &ln, T (
     T u1 = 0, u2 = 0, d1 = 0, d2 = 0;
 #pragma unroll
     for (int o = 0; o < K; ++o) {      // record: K complex z values, then K complex y values
-      T a1, a2;
-      pair_terms(yr[o], yi[o], zr[o], zi[o], up[2 * K + 2 * o], up[2 * K + 2 * o + 1], up[2 * o], up[2 * o + 1], a1, a2);
-      u1 += a1;
-      u2 += a2;
-      pair_terms(yr[o], yi[o], zr[o], zi[o], dn[2 * K + 2 * o], dn[2 * K + 2 * o + 1], dn[2 * o], dn[2 * o + 1], a1, a2);
-      d1 += a1;
-      d2 += a2;
+      pair_terms_acc(yr[o], yi[o], zr[o], zi[o], up[2 * K + 2 * o], up[2 * K + 2 * o + 1], up[2 * o], up[2 * o + 1], u1,
+                     u2);
+      pair_terms_acc(yr[o], yi[o], zr[o], zi[o], dn[2 * K + 2 * o], dn[2 * K + 2 * o + 1], dn[2 * o], dn[2 * o + 1], d1,
+                     d2);
     }
     s1[G::R + JJ] = fma_(ln.whi[JJ], d1, ln.wlo[JJ] * u1);
     s2[G::R + JJ] = fma_(-ln.whi[JJ], d2, ln.wlo[JJ] * u2);
@@ -929,20 +933,22 @@ __device__ __forceinline__ void last_inner_lane(const Lane<T, Q, L, LD> &ln, T (
 // state and adjoint): their records travel in one exchange, so a step has half as
 // many LDS round trips.  Each result equals half_sweep on its own bit for bit.
 // LAST: also the lane-digit inner products of the final z and y (last_inner_lane).
-template <typename T, int Q, int L, int LD, bool REV, int C, bool HOP, bool LAST = false>
+// FIRST: the increments still equal their start values x (read in place of w).
+template <typename T, int Q, int L, int LD, bool REV, int C, bool HOP, bool LAST = false, bool FIRST = false>
 __device__ __forceinline__ void half_sweep2(const Lane<T, Q, L, LD> &ln, const Coef<T, Q, L, LD> &cf,
                                             const T *uar, const T *uai, const T *xar, const T *xai, T *war, T *wai,
                                             const T *ubr, const T *ubi, const T *xbr, const T *xbi, T *wbr,
                                             T *wbi, T *s1 = nullptr, T *s2 = nullptr) {
   using G = Geo<T, Q, L, LD>;
   constexpr int IN = (1 - C) * G::H, OUT = C * G::H;
+  const T *car = FIRST ? xar : war, *cai = FIRST ? xai : wai, *cbr = FIRST ? xbr : wbr, *cbi = FIRST ? xbi : wbi;
   T var[G::EPL], vai[G::EPL], vbr[G::EPL], vbi[G::EPL], rr[2 * G::H], ri[2 * G::H];
 #pragma unroll
   for (int o = 0; o < G::H; ++o) {
-    var[IN + o] = uar[IN + o] + war[IN + o];
-    vai[IN + o] = uai[IN + o] + wai[IN + o];
-    vbr[IN + o] = ubr[IN + o] + wbr[IN + o];
-    vbi[IN + o] = ubi[IN + o] + wbi[IN + o];
+    var[IN + o] = uar[IN + o] + car[IN + o];
+    vai[IN + o] = uai[IN + o] + cai[IN + o];
+    vbr[IN + o] = ubr[IN + o] + cbr[IN + o];
+    vbi[IN + o] = ubi[IN + o] + cbi[IN + o];
     rr[o] = var[IN + o];
     ri[o] = vai[IN + o];
     rr[G::H + o] = vbr[IN + o];
@@ -952,10 +958,10 @@ __device__ __forceinline__ void half_sweep2(const Lane<T, Q, L, LD> &ln, const C
   if constexpr (HOP) {
 #pragma unroll
     for (int o = 0; o < G::H; ++o) {
-      orr[o] = uar[OUT + o] + war[OUT + o];
-      ori[o] = uai[OUT + o] + wai[OUT + o];
-      orr[G::H + o] = ubr[OUT + o] + wbr[OUT + o];
-      ori[G::H + o] = ubi[OUT + o] + wbi[OUT + o];
+      orr[o] = uar[OUT + o] + car[OUT + o];
+      ori[o] = uai[OUT + o] + cai[OUT + o];
+      orr[G::H + o] = ubr[OUT + o] + cbr[OUT + o];
+      ori[G::H + o] = ubi[OUT + o] + cbi[OUT + o];
     }
   }
   T n[2 * (LD > 0 ? LD : 1)][4 * G::H];
@@ -1012,29 +1018,37 @@ __device__ __forceinline__ void solve_increment2(const Lane<T, Q, L, LD> &ln, in
     for (int e = 0; e < G::EPL; ++e) {
       ln.template scale_m1<REV>(e, ar[e], ai[e], xar[e], xai[e]);
       ln.template scale_m1<REV>(e, br[e], bi[e], xbr[e], xbi[e]);
-      war[e] = xar[e];
-      wai[e] = xai[e];
-      wbr[e] = xbr[e];
-      wbi[e] = xbi[e];
     }
-    int h = 0;
-    if constexpr (fused_inner<T, L>()) {
-      for (; h + 2 < nit; h += 2) {
-        half_sweep2<T, Q, L, LD, REV, 0, HOP>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
-        half_sweep2<T, Q, L, LD, REV, 1, HOP>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+    // Half sweeps alternate colour 0, 1, 0, ...; the first reads x in place of w, and w's
+    // colour 1 keeps x until the second writes it (copied only where it is read first: a
+    // single half sweep, or the dipole terms, which read the refreshed colour's own values).
+    // When fused_inner, the last one also takes the lane-digit inner products.
+    constexpr bool FI = fused_inner<T, L>();
+    if (HOP || nit < 2) {
+#pragma unroll
+      for (int o = G::H; o < G::EPL; ++o) {
+        war[o] = xar[o];
+        wai[o] = xai[o];
+        wbr[o] = xbr[o];
+        wbi[o] = xbi[o];
       }
-      if (nit - h == 2) {
-        half_sweep2<T, Q, L, LD, REV, 0, HOP>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
-        half_sweep2<T, Q, L, LD, REV, 1, HOP, true>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi, s1, s2);
-      } else {
-        half_sweep2<T, Q, L, LD, REV, 0, HOP, true>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi, s1, s2);
-      }
+    }
+    if (nit < 2) {
+      half_sweep2<T, Q, L, LD, REV, 0, HOP, FI, true>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi,
+                                                      s1, s2);
+      return;
+    }
+    half_sweep2<T, Q, L, LD, REV, 0, HOP, false, true>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+    int h = 1;
+    for (; h + 2 < nit; h += 2) {
+      half_sweep2<T, Q, L, LD, REV, 1, HOP>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+      half_sweep2<T, Q, L, LD, REV, 0, HOP>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+    }
+    if (nit - h == 2) {
+      half_sweep2<T, Q, L, LD, REV, 1, HOP>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+      half_sweep2<T, Q, L, LD, REV, 0, HOP, FI>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi, s1, s2);
     } else {
-      for (; h + 1 < nit; h += 2) {
-        half_sweep2<T, Q, L, LD, REV, 0, HOP>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
-        half_sweep2<T, Q, L, LD, REV, 1, HOP>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
-      }
-      if (h < nit) half_sweep2<T, Q, L, LD, REV, 0, HOP>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+      half_sweep2<T, Q, L, LD, REV, 1, HOP, FI>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi, s1, s2);
     }
   } else {
     solve_increment<T, Q, L, LD, REV, HOP>(ln, nit, cf, ar, ai, war, wai);
@@ -1286,13 +1300,18 @@ __device__ __forceinline__ void inner_lane_digits(const Lane<T, Q, L, LD> &ln, c
 // pair and writes it to the series (one coalesced store per flush).
 template <typename T>
 constexpr int red_elems() { return sizeof(T) == 4 ? 36 * 64 : 24 * 64; }   // 9 KB (FP32), 12 KB (FP64) per wavefront
+// The one-wavefront FP32 sweep without the dipole terms (k_backward) buffers 64/(2q) steps, so
+// every lane takes part in a flush (16.3 KB; eight such wavefronts with their exchange buffers
+// fit one CU's LDS).
+template <typename T, bool HOP>
+constexpr int red_one_elems() { return sizeof(T) == 4 && !HOP ? 65 * 64 : red_elems<T>(); }
 
-template <typename T, int Q>
+template <typename T, int Q, int RE = red_elems<T>()>
 struct SeriesBuf {
   static constexpr int NV = 2 * Q;               // values per step
   static constexpr int VS = 65;                  // elements per (step, value) row: 64 lanes + 1 (bank offset)
   static constexpr int RS = NV * VS;             // elements per buffered step
-  static constexpr int RB = (red_elems<T>() / RS < 64 / NV) ? red_elems<T>() / RS : 64 / NV;   // steps per flush
+  static constexpr int RB = (RE / RS < 64 / NV) ? RE / RS : 64 / NV;   // steps per flush
   static_assert(RB >= 1, "reduction buffer too small");
 };
 
@@ -1368,11 +1387,13 @@ __device__ __forceinline__ void ckpt_step(const DevSys &s, int m, const Lane<T, 
 
 // The step's 2q inner products of this lane into the wavefront's series buffer; every
 // RB steps, lane i sums one buffered (step, value) row over the 64 lanes in FP64, in
-// lane order, and stores it (idx = k - k0, len = window length).  Only this
-// wavefront touches `red`, and its LDS operations complete in order.
-template <typename T, int Q>
-__device__ __forceinline__ void series_put(T *red, double *ser, int lane, int idx, int len, const T *s1, const T *s2) {
-  using SB = SeriesBuf<T, Q>;
+// lane order, and stores it in the propagation precision (idx = k - k0, len = window
+// length): the lane values are products of that precision, so the stored sum keeps their
+// accuracy, and the sums over column groups and steps that follow run in FP64.  Only
+// this wavefront touches `red`, and its LDS operations complete in order.
+template <typename T, int Q, int RE = red_elems<T>()>
+__device__ __forceinline__ void series_put(T *red, T *ser, int lane, int idx, int len, const T *s1, const T *s2) {
+  using SB = SeriesBuf<T, Q, RE>;
   T *slot = red + (idx % SB::RB) * SB::RS + lane;
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
@@ -1387,7 +1408,7 @@ __device__ __forceinline__ void series_put(T *red, double *ser, int lane, int id
       double acc = 0.0;
 #pragma unroll 8
       for (int l = 0; l < 64; ++l) acc += (double)col[l];
-      ser[(size_t)(idx + r) * SB::NV + vv] = acc;
+      ser[(size_t)(idx + r) * SB::NV + vv] = (T)acc;
     }
     wave_sync();
   }
@@ -1403,7 +1424,7 @@ __device__ __forceinline__ void series_put(T *red, double *ser, int lane, int id
 template <typename G, int Q>
 constexpr bool split_rhs() { return G::CPW >= 2; }
 
-template <typename T, int Q, int L, int LD, bool HOP>
+template <typename T, int Q, int L, int LD, bool HOP, int RE = red_elems<T>()>
 __device__ __forceinline__ void backward_item_split(const DevSys &s, int m, int cg, T *red, T *xb) {
   using G = Geo<T, Q, L, LD>;
   const int item = m * s.ncg_b + cg;
@@ -1417,7 +1438,7 @@ __device__ __forceinline__ void backward_item_split(const DevSys &s, int m, int 
   const long long k0 = s.kstart[m], k1 = s.kstart[m + 1];
   const int kit = kit_of(s);
   const T *ctrl = reinterpret_cast<const T *>(s.ctrl);
-  double *ser = s.series + (size_t)item * s.maxlen * 2 * Q;
+  T *ser = reinterpret_cast<T *>(s.series) + (size_t)item * s.maxlen * 2 * Q;
   CkptPos cp(s, k0, k1);
   typename C2<T>::type cnext[Q];
   load_ctrl<T, Q>(ctrl, k1 - 1, cnext);
@@ -1474,7 +1495,7 @@ __device__ __forceinline__ void backward_item_split(const DevSys &s, int m, int 
       s1[j] = adj ? (T)0 : s1[j];
       s2[j] = adj ? (T)0 : s2[j];
     }
-    series_put<T, Q>(red, ser, ln.lane, (int)(k - k0), (int)(k1 - k0), s1, s2);
+    series_put<T, Q, RE>(red, ser, ln.lane, (int)(k - k0), (int)(k1 - k0), s1, s2);
 #pragma unroll
     for (int e = 0; e < G::EPL; ++e) {
       ar[e] += 2.0 * (double)wr[e];
@@ -1502,11 +1523,12 @@ __device__ __forceinline__ void backward_item_split(const DevSys &s, int m, int 
 // Re<z, i dH z>/E = 0 to the control gradient (dH Hermitian); only gamma V/E^2 is
 // propagated, and the W-gradient adds the dropped part back exactly:
 // Lambda^M(t_{M-1}) = -W^{M-1}/E + (propagated part)  (App. B, eq. back-prop-2).
-template <typename T, int Q, int L, int LD, bool HOP>
+// red: RE elements of series buffer (LDS).
+template <typename T, int Q, int L, int LD, bool HOP, int RE = red_elems<T>()>
 __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T *red, T *xb) {
   using G = Geo<T, Q, L, LD>;
   if constexpr (split_rhs<G, Q>()) {
-    backward_item_split<T, Q, L, LD, HOP>(s, m, cg, red, xb);
+    backward_item_split<T, Q, L, LD, HOP, RE>(s, m, cg, red, xb);
     return;
   }
   const int item = m * s.ncg_b + cg;
@@ -1520,7 +1542,7 @@ __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T 
   const long long k0 = s.kstart[m], k1 = s.kstart[m + 1];
   const int kit = kit_of(s);
   const T *ctrl = reinterpret_cast<const T *>(s.ctrl);
-  double *ser = s.series + (size_t)item * s.maxlen * 2 * Q;
+  T *ser = reinterpret_cast<T *>(s.series) + (size_t)item * s.maxlen * 2 * Q;
   CkptPos cp(s, k0, k1);
 
   for (long long k = k1 - 1; k >= k0; --k) {      // (one column per wavefront: the controls are not loaded ahead)
@@ -1551,7 +1573,7 @@ __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T 
     // A = <y, a_j z> = sum conj(y_r) sqrt(l+1) z_{r+st},  B = <y, a_j^+ z> = sum sqrt(l+1) conj(y_{r+st}) z_r
     inner_register_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
     if constexpr (!fused_inner<T, L>()) inner_lane_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
-    series_put<T, Q>(red, ser, ln.lane, (int)(k - k0), (int)(k1 - k0), s1, s2);
+    series_put<T, Q, RE>(red, ser, ln.lane, (int)(k - k0), (int)(k1 - k0), s1, s2);
 #pragma unroll
     for (int e = 0; e < G::EPL; ++e) {
       udr[e] += 2.0 * (double)wur[e];
@@ -1574,10 +1596,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HOP && sizeo
 void k_backward(DevSys s, int nitems) {
   const int item = xcd_item(blockIdx.x, gridDim.x);
   if (item >= nitems) return;
-  __shared__ T red[red_elems<T>()];
+  __shared__ T red[red_one_elems<T, HOP>()];
   __shared__ __align__(16) T xb[xchg_bytes<T, HOP>() / sizeof(T)];
   xchg_clear<T, HOP>(xb);
-  backward_item<T, Q, L, LD, HOP>(s, item / s.ncg_b, item % s.ncg_b, red, xb);
+  backward_item<T, Q, L, LD, HOP, red_one_elems<T, HOP>()>(s, item / s.ncg_b, item % s.ncg_b, red, xb);
 }
 
 // Two wavefronts per (window, column group) for the one-column-per-wavefront layout
@@ -1600,7 +1622,7 @@ __device__ __forceinline__ void backward_item_xw(const DevSys &s, int m, int cg,
   const long long k0 = s.kstart[m], k1 = s.kstart[m + 1];
   const int kit = kit_of(s);
   const T *ctrl = reinterpret_cast<const T *>(s.ctrl);
-  double *ser = s.series + (size_t)item * s.maxlen * 2 * Q;
+  T *ser = reinterpret_cast<T *>(s.series) + (size_t)item * s.maxlen * 2 * Q;
   CkptPos cp(s, k0, k1);
   for (long long k = k1 - 1; k >= k0; --k) {
     typename C2<T>::type ccur[Q];
@@ -1675,7 +1697,7 @@ __device__ __forceinline__ void backward_item_sx(const DevSys &s, int m, int cg,
   if (wv == 0) backward_start<T, Q, L, LD>(s, m, ln, adj, ar, ai);
   const int kit = kit_of(s);
   const T *ctrl = reinterpret_cast<const T *>(s.ctrl);
-  double *ser = s.series + (size_t)item * s.maxlen * 2 * Q;
+  T *ser = reinterpret_cast<T *>(s.series) + (size_t)item * s.maxlen * 2 * Q;
   CkptPos cp(s, k0, k1);
   typename C2<T>::type cnext[Q];
   if (wv == 0) load_ctrl<T, Q>(ctrl, k1 - 1, cnext);
@@ -1791,7 +1813,7 @@ __device__ __forceinline__ void backward_item_x3(const DevSys &s, int m, int cg,
   if (wv < 2) backward_start<T, Q, L, LD>(s, m, ln, wv == 1, ar, ai);
   const int kit = kit_of(s);
   const T *ctrl = reinterpret_cast<const T *>(s.ctrl);
-  double *ser = s.series + (size_t)item * s.maxlen * 2 * Q;
+  T *ser = reinterpret_cast<T *>(s.series) + (size_t)item * s.maxlen * 2 * Q;
   T *own = (wv == 0 ? zb : yb) + roff;
   CkptPos cp(s, k0, k1);
   for (long long k = k1 - 1; k >= k0 - 1; --k) {
@@ -2003,12 +2025,24 @@ __device__ void boundary_partial_block(const DevSys &s, int m) {
 }
 
 __device__ void boundary_final_block(const DevSys &s) {
-  if (threadIdx.x != 0) return;
+  // the per-window penalties are copied by all threads and summed by one, in window order,
+  // from LDS (a serial loop over device memory would wait on every load in turn)
+  __shared__ double pw[256];
   double pen = 0.0;
-  for (int m = 0; m < s.M - 1; ++m) {
-    pen += s.partials[4 * m];
-    s.scal[6 + m] = s.partials[4 * m];
+  for (int m0 = 0; m0 < s.M - 1; m0 += 256) {
+    const int m = m0 + (int)threadIdx.x;
+    if (m < s.M - 1) {
+      pw[threadIdx.x] = s.partials[4 * m];
+      s.scal[6 + m] = pw[threadIdx.x];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int n = min(256, s.M - 1 - m0);
+      for (int i = 0; i < n; ++i) pen += pw[i];
+    }
+    __syncthreads();
   }
+  if (threadIdx.x != 0) return;
   const double E = (double)s.E;
   const double nrm = s.partials[4 * (s.M - 1)], gr = s.partials[4 * (s.M - 1) + 1], gi = s.partials[4 * (s.M - 1) + 2];
   const double J = nrm / E - (gr * gr + gi * gi) / (E * E);
@@ -2021,8 +2055,12 @@ __device__ void boundary_final_block(const DevSys &s) {
   s.scal[5] = gi;
 }
 
-// xy[k] = sum over the window's column groups of the per-wavefront series.
+// xy[k] = sum over the window's column groups of the per-wavefront series (stored in the
+// propagation precision T), in FP64 and group order; one thread per step, reading each
+// group's record of 2q values in pairs.
+template <typename T>
 __device__ void series_reduce_block(const DevSys &s, int blk) {
+  using V2 = typename C2<T>::type;
   const long long k = (long long)blk * 256 + threadIdx.x;
   if (k >= s.NT) return;
   const int m = (int)(((k + 1) * s.M - 1) / s.NT);   // window of step k under the floor split
@@ -2032,10 +2070,15 @@ __device__ void series_reduce_block(const DevSys &s, int blk) {
 #pragma unroll
   for (int i = 0; i < 12; ++i) acc[i] = 0.0;
   for (int cg = 0; cg < s.ncg_b; ++cg) {     // one contiguous record of 2q values per column group
-    const double *src = s.series + (((size_t)m * s.ncg_b + cg) * s.maxlen + kk) * w;
+    const V2 *src = reinterpret_cast<const V2 *>(reinterpret_cast<const T *>(s.series) +
+                                                 (((size_t)m * s.ncg_b + cg) * s.maxlen + kk) * w);
 #pragma unroll
-    for (int i = 0; i < 12; ++i)
-      if (i < w) acc[i] += src[i];
+    for (int i = 0; i < 6; ++i)
+      if (2 * i < w) {
+        const V2 v = src[i];
+        acc[2 * i] += (double)v.x;
+        acc[2 * i + 1] += (double)v.y;
+      }
   }
 #pragma unroll
   for (int i = 0; i < 12; ++i)
@@ -2097,7 +2140,7 @@ __device__ __forceinline__ void small_block(const DevSys &s, int blk) {
   else if constexpr (K == SK_KIT) kit_block(s);
   else if constexpr (K == SK_BPARTIAL) boundary_partial_block(s, blk);
   else if constexpr (K == SK_BFINAL) boundary_final_block(s);
-  else if constexpr (K == SK_SERIES) series_reduce_block(s, blk);
+  else if constexpr (K == SK_SERIES) series_reduce_block<T>(s, blk);
   else if constexpr (K == SK_PROJECT) project_block(s, blk);
   else grad_W_block(s, blk);
 }

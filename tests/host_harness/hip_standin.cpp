@@ -165,7 +165,7 @@ static void check_sys(const DevSys &s) {
   check_range(s.Ufin, sizeof(double) * 2 * nst, "Ufin");
   check_range(s.lam0, sizeof(double) * 2 * nst, "lam0");
   check_range(s.scal, sizeof(double) * (5 + s.M), "scal");
-  check_range(s.series, sizeof(double) * (size_t)s.M * s.ncg_b * s.maxlen * 2 * s.q, "series");
+  check_range(s.series, (s.fp64 ? sizeof(double) : sizeof(float)) * (size_t)s.M * s.ncg_b * s.maxlen * 2 * s.q, "series");
   check_range(s.status, sizeof(int), "status");
   check_range(s.kit, sizeof(int), "kit");
 }
