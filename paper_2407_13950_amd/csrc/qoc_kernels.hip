@@ -1019,12 +1019,34 @@ __device__ __forceinline__ void solve_increment2(const Lane<T, Q, L, LD> &ln, in
       ln.template scale_m1<REV>(e, ar[e], ai[e], xar[e], xai[e]);
       ln.template scale_m1<REV>(e, br[e], bi[e], xbr[e], xbi[e]);
     }
-    // Half sweeps alternate colour 0, 1, 0, ...; the first reads x in place of w, and w's
-    // colour 1 keeps x until the second writes it (copied only where it is read first: a
-    // single half sweep, or the dipole terms, which read the refreshed colour's own values).
-    // When fused_inner, the last one also takes the lane-digit inner products.
+    // Half sweeps alternate colour 0, 1, 0, ...; when fused_inner, the last one also takes
+    // the lane-digit inner products.
     constexpr bool FI = fused_inner<T, L>();
-    if (HOP || nit < 2) {
+    if constexpr (HOP) {
+      // the dipole terms read the refreshed colour's own current values: w starts as x
+#pragma unroll
+      for (int e = 0; e < G::EPL; ++e) {
+        war[e] = xar[e];
+        wai[e] = xai[e];
+        wbr[e] = xbr[e];
+        wbi[e] = xbi[e];
+      }
+      int h = 0;
+      for (; h + 2 < nit; h += 2) {
+        half_sweep2<T, Q, L, LD, REV, 0, HOP>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+        half_sweep2<T, Q, L, LD, REV, 1, HOP>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+      }
+      if (nit - h == 2) {
+        half_sweep2<T, Q, L, LD, REV, 0, HOP>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi);
+        half_sweep2<T, Q, L, LD, REV, 1, HOP, FI>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi, s1, s2);
+      } else {
+        half_sweep2<T, Q, L, LD, REV, 0, HOP, FI>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi, s1, s2);
+      }
+      return;
+    }
+    // The first half sweep reads x in place of w; w's colour 1 keeps x until the second
+    // writes it (copied only when there is a single half sweep).
+    if (nit < 2) {
 #pragma unroll
       for (int o = G::H; o < G::EPL; ++o) {
         war[o] = xar[o];
@@ -1032,8 +1054,6 @@ __device__ __forceinline__ void solve_increment2(const Lane<T, Q, L, LD> &ln, in
         wbr[o] = xbr[o];
         wbi[o] = xbi[o];
       }
-    }
-    if (nit < 2) {
       half_sweep2<T, Q, L, LD, REV, 0, HOP, FI, true>(ln, cf, ar, ai, xar, xai, war, wai, br, bi, xbr, xbi, wbr, wbi,
                                                       s1, s2);
       return;
@@ -2097,15 +2117,23 @@ __device__ void project_block(const DevSys &s, int b) {
   const long long klo = max(0LL, (long long)floor((sp - 2.0) * r - 0.5));
   const long long khi = min(s.NT - 1, (long long)ceil((sp + 1.0) * r - 0.5));
   double a1 = 0.0, a2 = 0.0;
-  for (long long k = klo + threadIdx.x; k <= khi; k += 256) {
+  // the carrier phase advances by om * 256 dt between a thread's steps: one sincos per
+  // thread, then a rotation per step (about 20 per thread at 4 qubits; error ~1e-15)
+  const long long k0 = klo + threadIdx.x;
+  double sn, cs, sd, cd;
+  sincos(om * ((k0 + 0.5) * s.dt), &sn, &cs);
+  sincos(om * (256.0 * s.dt), &sd, &cd);
+  for (long long k = k0; k <= khi; k += 256) {
     const double t = (k + 0.5) * s.dt;
     const double bs = bspline2(t / s.dtau + 0.5 - sp);
-    if (bs == 0.0) continue;
-    double sn, cs;
-    sincos(om * t, &sn, &cs);
-    const double s1 = s.xy[(size_t)k * 2 * s.q + 2 * j], s2 = s.xy[(size_t)k * 2 * s.q + 2 * j + 1];
-    a1 += bs * (cs * s1 + sn * s2);
-    a2 += bs * (-sn * s1 + cs * s2);
+    if (bs != 0.0) {
+      const double s1 = s.xy[(size_t)k * 2 * s.q + 2 * j], s2 = s.xy[(size_t)k * 2 * s.q + 2 * j + 1];
+      a1 += bs * (cs * s1 + sn * s2);
+      a2 += bs * (-sn * s1 + cs * s2);
+    }
+    const double sn2 = sn * cd + cs * sd;
+    cs = cs * cd - sn * sd;
+    sn = sn2;
   }
   a1 = block_sum<256>(a1, sh);
   a2 = block_sum<256>(a2, sh);
