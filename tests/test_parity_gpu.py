@@ -201,3 +201,16 @@ def test_minimal_forced_counts_run(n):
     w, alpha, W = small_case(4, 4, 60, 3)
     P, t, ga, gW = run_gpu(w, alpha, W, "fp32", fixed_point_iters=n)
     assert np.isfinite(P) and np.all(np.isfinite(ga)) and np.all(np.isfinite(gW.view(np.float64)))
+
+
+def test_projection_over_long_spline_supports():
+    """Four splines over 60,000 steps: each projection thread advances its carrier phase by a
+    rotation through about 350 steps (eq. grad-int projected on the B-spline x carrier basis,
+    eq. dj-ctrl); the FP64 control gradient still meets the 1e-10 bound."""
+    w, alpha, W = small_case(2, 3, 60000, 4, d1=4)
+    P0, t0, ga0, gW0 = O.gradient(w, alpha, W)
+    P, t, ga, gW = run_gpu(w, alpha, W, "fp64")
+    print(f"{w.name}: grad_alpha rel {rel(ga, ga0):.2e}", flush=True)
+    assert abs(P - P0) <= 1e-11 * abs(P0)
+    assert rel(ga, ga0) <= 1e-10
+    assert rel(gW, gW0) <= 1e-10
