@@ -394,12 +394,13 @@ struct DppGets {
   }
 };
 
-// Writes this lane's K complex values to the exchange.  FP32 also requests all
-// neighbours' records at once (n[2jj]: lane digit jj one step up, n[2jj+1]: one
-// step down), so their latencies overlap with the lane-independent work the caller
-// does before lane_digit_terms; FP64 (twice the registers per record) reads each
-// record only where it is used.
-template <typename T> struct XPre { static constexpr bool value = sizeof(T) == 4; };
+// Writes this lane's K complex values to the exchange.  FP32, and FP64 records of at most
+// three complex values (one right-hand side), also request all neighbours' records at once
+// (n[2jj]: lane digit jj one step up, n[2jj+1]: one step down), so their latencies overlap
+// with the lane-independent work the caller does before lane_digit_terms; larger FP64
+// records (both right-hand sides of the backward sweep: twice the registers) are read only
+// where they are used.
+template <typename T, int K> struct XPre { static constexpr bool value = sizeof(T) == 4 || K <= 3; };
 
 // Planes after the first record's: a second record of KO complex values (the
 // dipole exchange's own-colour values) rides in the same exchange.
@@ -432,7 +433,7 @@ __device__ __forceinline__ void lane_exchange(const Lane<T, Q, L, LD> &ln, const
       xput<T, 2 * KO>(ln.xb + xtail<T, K>(), ln.lane, rec2);
     }
     wave_sync();
-    if constexpr (XPre<T>::value) {
+    if constexpr (XPre<T, K>::value) {
       LaneGets<T, LD, K, 0>::load(ln, n);
       // keep the caller's register-digit arithmetic after the reads' issue, where it covers
       // their latency (left alone, the scheduler places it between the write and the reads)
@@ -447,12 +448,12 @@ __device__ __forceinline__ void lane_digit_terms(const Lane<T, Q, L, LD> &ln, co
                                                  const T *hir, const T *hii, T (*n)[2 * K], T *Sr, T *Si) {
   if constexpr (JJ < LD) {
     constexpr int ST = Geo<T, Q, L, LD>::lstride(JJ);
-    if constexpr (!XPre<T>::value) {
+    if constexpr (!XPre<T, K>::value) {
       xget<T, 2 * K, ST>(ln.xb, ln.lane, n[0]);
       xget<T, 2 * K, -ST>(ln.xb, ln.lane, n[1]);
     }
-    const T *up = XPre<T>::value ? n[2 * JJ] : n[0];
-    const T *dn = XPre<T>::value ? n[2 * JJ + 1] : n[1];
+    const T *up = XPre<T, K>::value ? n[2 * JJ] : n[0];
+    const T *dn = XPre<T, K>::value ? n[2 * JJ + 1] : n[1];
     if constexpr (dpp_layout<T, L, LD>()) {
       // two levels: up and dn are the same lane and one of the two weights is zero, so
       // one product with their sum gives the same value (half the multiply-adds)
@@ -467,7 +468,7 @@ __device__ __forceinline__ void lane_digit_terms(const Lane<T, Q, L, LD> &ln, co
       }
     }
     lane_digit_terms<T, Q, L, LD, K, JJ + 1>(ln, lor, loi, hir, hii, n, Sr, Si);
-  } else if constexpr (LD > 0 && !XPre<T>::value) {
+  } else if constexpr (LD > 0 && !XPre<T, K>::value) {
     wave_sync();
   }
 }
@@ -903,7 +904,7 @@ __device__ __forceinline__ void last_inner_lane(const Lane<T, Q, L, LD> &ln, T (
   if constexpr (JJ < LD) {
     constexpr int ST = G::lstride(JJ);
     T up[4 * K], dn[4 * K];
-    if constexpr (XPre<T>::value) {
+    if constexpr (XPre<T, 2 * K>::value) {
 #pragma unroll
       for (int i = 0; i < 4 * K; ++i) {
         up[i] = n[2 * JJ][i];
@@ -924,7 +925,7 @@ __device__ __forceinline__ void last_inner_lane(const Lane<T, Q, L, LD> &ln, T (
     s1[G::R + JJ] = fma_(ln.whi[JJ], d1, ln.wlo[JJ] * u1);
     s2[G::R + JJ] = fma_(-ln.whi[JJ], d2, ln.wlo[JJ] * u2);
     last_inner_lane<T, Q, L, LD, K, JJ + 1>(ln, n, zr, zi, yr, yi, s1, s2);
-  } else if constexpr (LD > 0 && !XPre<T>::value) {
+  } else if constexpr (LD > 0 && !XPre<T, 2 * K>::value) {
     wave_sync();
   }
 }
@@ -1001,7 +1002,7 @@ __device__ __forceinline__ void half_sweep2(const Lane<T, Q, L, LD> &ln, const C
 // Lane-digit inner products taken inside the last half sweep: red-black layout in
 // FP32 (FP64 lacks the registers to keep the records, it exchanges z and y again).
 template <typename T, int L>
-constexpr bool fused_inner() { return (L % 2) == 0 && XPre<T>::value; }
+constexpr bool fused_inner() { return (L % 2) == 0 && sizeof(T) == 4; }
 
 // Two right-hand sides with the same matrix (a: state, b: adjoint); each result is
 // bit-identical to solve_increment on its own.  When fused_inner, the lane-digit
