@@ -78,11 +78,12 @@ struct Geo {
   static constexpr int rstride(int j) { return cipow(L, R - 1 - j); }   // register digit j < R
   static constexpr int rdigit(int e, int j) { return (e / rstride(j)) % L; }
   static constexpr int lstride(int jj) { return cipow(L, LD - 1 - jj); } // lane digit jj (qubit R+jj)
-  // Red-black slot layout (even L).  An entry is red or black by the parity of its
-  // digit sum; every ladder term couples the two colours.  Slot i = c*H + s0*RT + t
-  // holds the entry of colour c whose leading register digit is l0 = 2*s0 + b and
-  // whose remaining register digits form t, with b = (lane parity) ^ par(t) ^ c.
-  static constexpr bool RB = (L % 2) == 0;
+  // Red-black slot layout (even L, at least one register digit).  An entry is red or black
+  // by the parity of its digit sum; every ladder term couples the two colours.  Slot
+  // i = c*H + s0*RT + t holds the entry of colour c whose leading register digit is
+  // l0 = 2*s0 + b and whose remaining register digits form t, with b = (lane parity) ^
+  // par(t) ^ c.  Layouts with every digit on lanes (one entry per lane) iterate Jacobi-style.
+  static constexpr bool RB = (L % 2) == 0 && R >= 1;
   static constexpr int H = EPL / 2;              // slots per colour
   static constexpr int HALF = L / 2;             // values of s0
   static constexpr int RT = EPL / L;             // tuples of register digits 1..R-1
@@ -542,11 +543,12 @@ __device__ __forceinline__ void hop_terms(const Lane<T, Q, L, LD> &ln, const T *
   constexpr int NV = 2 * NO * NRHS;
   constexpr int R = G::R;
   static_assert(!RBL || G::RB, "a colour needs the red-black layout");
-  static_assert(R == 1 || Q < 2, "every layout keeps one register digit: no pair of two register digits");
+  static_assert(R <= 1 || Q < 2, "layouts keep at most one register digit: no pair of two register digits");
   if constexpr (LD > 0) {
     // pair (0, 1): the register digit and lane digit 0.  A reads the lane one step
-    // down in lane digit 0 (l_1 - 1), B the lane one step up.
-    {
+    // down in lane digit 0 (l_1 - 1), B the lane one step up.  (No register digit: every
+    // pair is one of lane digits, below.)
+    if constexpr (R == 1) {
       constexpr int ST = G::lstride(0);
       T dn[NV], up[NV];
       if constexpr (dpp_layout<T, L, LD>()) {   // two levels: both read lane ^ ST
@@ -1001,8 +1003,8 @@ __device__ __forceinline__ void half_sweep2(const Lane<T, Q, L, LD> &ln, const C
 
 // Lane-digit inner products taken inside the last half sweep: red-black layout in
 // FP32 (FP64 lacks the registers to keep the records, it exchanges z and y again).
-template <typename T, int L>
-constexpr bool fused_inner() { return (L % 2) == 0 && sizeof(T) == 4; }
+template <typename T, int Q, int L, int LD>
+constexpr bool fused_inner() { return Geo<T, Q, L, LD>::RB && sizeof(T) == 4; }
 
 // Two right-hand sides with the same matrix (a: state, b: adjoint); each result is
 // bit-identical to solve_increment on its own.  When fused_inner, the lane-digit
@@ -1022,7 +1024,7 @@ __device__ __forceinline__ void solve_increment2(const Lane<T, Q, L, LD> &ln, in
     }
     // Half sweeps alternate colour 0, 1, 0, ...; when fused_inner, the last one also takes
     // the lane-digit inner products.
-    constexpr bool FI = fused_inner<T, L>();
+    constexpr bool FI = fused_inner<T, Q, L, LD>();
     if constexpr (HOP) {
       // the dipole terms read the refreshed colour's own current values: w starts as x
 #pragma unroll
@@ -1593,7 +1595,7 @@ __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T 
     // inner products per qubit: s1 = Im(A + B), s2 = Re(A - B) with
     // A = <y, a_j z> = sum conj(y_r) sqrt(l+1) z_{r+st},  B = <y, a_j^+ z> = sum sqrt(l+1) conj(y_{r+st}) z_r
     inner_register_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
-    if constexpr (!fused_inner<T, L>()) inner_lane_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
+    if constexpr (!fused_inner<T, Q, L, LD>()) inner_lane_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
     series_put<T, Q, RE>(red, ser, ln.lane, (int)(k - k0), (int)(k1 - k0), s1, s2);
 #pragma unroll
     for (int e = 0; e < G::EPL; ++e) {
@@ -1928,7 +1930,7 @@ __device__ void kit_block(const DevSys &s) {
   if (threadIdx.x != 0) return;
   const double rho = (double)__uint_as_float(*s.rho_bits) * (1.0 + 1e-6);
   *s.rho_bits = 0u;                  // reset for the next evaluation
-  const bool rb = (s.L % 2) == 0;
+  const bool rb = (s.L % 2) == 0 && s.q - s.ld >= 1;   // the layout's red-black ordering (Geo::RB)
   const double beta = s.beta, tau = rho + beta;
   int K = 1;
   double err;
@@ -2206,11 +2208,12 @@ Kernels make() {
 // per state (the backward sweep keeps about 16 such arrays live).  Two-level
 // systems use two entries per lane: their windows are latency-bound chains (few
 // wavefronts, several columns each), and halving a lane's entries halves its
-// instructions per step.
+// instructions per step.  For the same reason the 2-qubit 3-level and 3-qubit
+// 4-level systems put every digit on lanes (one entry per lane, Jacobi iteration).
 #define QOC_SHAPES(X)   \
   X(1, 2, 0) X(1, 3, 0) X(1, 4, 0) \
-  X(2, 2, 1) X(2, 3, 1) X(2, 4, 1) \
-  X(3, 2, 2) X(3, 3, 2) X(3, 4, 2) \
+  X(2, 2, 1) X(2, 3, 2) X(2, 4, 1) \
+  X(3, 2, 2) X(3, 3, 2) X(3, 4, 3) \
   X(4, 2, 3) X(4, 3, 3) X(4, 4, 3) \
   X(5, 2, 4) X(6, 2, 5)
 

@@ -128,8 +128,8 @@ namespace qoc {
 // The layouts of the kernel file: lane digits per (q, L) and the dipole variant's index.
 bool layout_for(int q, int L, int fp64, int hop, int *ld, int *cpw, int *shape) {
   (void)fp64;
-  static const int table[][3] = {{1, 2, 0}, {1, 3, 0}, {1, 4, 0}, {2, 2, 1}, {2, 3, 1}, {2, 4, 1}, {3, 2, 2},
-                                 {3, 3, 2}, {3, 4, 2}, {4, 2, 3}, {4, 3, 3}, {4, 4, 3}, {5, 2, 4}, {6, 2, 5}};
+  static const int table[][3] = {{1, 2, 0}, {1, 3, 0}, {1, 4, 0}, {2, 2, 1}, {2, 3, 2}, {2, 4, 1}, {3, 2, 2},
+                                 {3, 3, 2}, {3, 4, 3}, {4, 2, 3}, {4, 3, 3}, {4, 4, 3}, {5, 2, 4}, {6, 2, 5}};
   const int n = (int)(sizeof table / sizeof table[0]);
   for (int i = 0; i < n; ++i)
     if (table[i][0] == q && table[i][1] == L) {

@@ -41,7 +41,7 @@ def test_forced_schedules_match_oracle(prec, dip, sched):
     assert abs(P - P0) <= tol_P * abs(P0) and g <= tol_g
 
 
-SPLIT_SHAPES = [(1, 3, 100, 3), (2, 3, 403, 5), (2, 4, 210, 4), (3, 2, 150, 5), (3, 4, 300, 7), (4, 2, 160, 4),
+SPLIT_SHAPES = [(1, 3, 100, 3), (2, 3, 403, 5), (2, 4, 210, 4), (3, 2, 150, 5), (3, 3, 180, 4), (4, 2, 160, 4),
                 (4, 3, 120, 3), (5, 2, 120, 3), (6, 2, 90, 2)]
 
 
@@ -68,7 +68,8 @@ def test_schedules_on_multi_column_layouts_match_oracle(q, L, n_steps, M, prec, 
 
 
 @pytest.mark.parametrize("q,L,sched", [(4, 4, "one_wave"), (4, 4, "two_waves"), (4, 4, "three_waves"),
-                                        (3, 4, "one_wave"), (3, 4, "two_waves"), (2, 2, "two_waves")])
+                                        (3, 4, "one_wave"), (3, 4, "two_waves"), (3, 4, "three_waves"),
+                                        (2, 3, "two_waves"), (2, 2, "two_waves")])
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_schedules_with_a_single_window(q, L, sched, prec):
     """M = 1: no window states, the only window's terminal condition is the infidelity's."""
@@ -114,7 +115,7 @@ def test_schedule_query_and_errors():
         s = qoc.System(w.replace(n_windows=M, n_steps=10 * M), precision="fp64")
         assert s.schedule() == want, (M, s.schedule())
         s.close()
-    w3, _, _ = PG.small_case(3, 4, 64, 4)                    # four columns per wavefront
+    w3, _, _ = PG.small_case(3, 3, 64, 4)                    # 3 levels: four columns per wavefront
     s = qoc.System(w3, precision="fp32")
     assert s.schedules() == ["one_wave", "two_waves"] and s.schedule() == "two_waves"   # 4 x 4 items
     with pytest.raises(qoc.QocError) as e:
@@ -178,7 +179,7 @@ def _check_equal_to_solo(members, systems):
 def test_batch_with_forced_schedules_equals_solo():
     members = _members()
     systems = _open(members)
-    assert [s.schedule() for s in systems] == ["one_wave", "two_waves", "three_waves", "two_waves", "two_waves",
+    assert [s.schedule() for s in systems] == ["one_wave", "two_waves", "three_waves", "three_waves", "two_waves",
                                                "three_waves", "two_waves", "two_waves", "one_wave"]
     b = qoc.Batch(max_contexts=12, max_items=4096)
     b.run(systems)
@@ -195,7 +196,7 @@ def test_tuner_choices_are_valid_and_keep_bit_identity():
     r = autotune.tune_system(systems[0], reps=2, warmup=1)
     assert r["choice"] in ("one_wave", "two_waves", "three_waves") and systems[0].schedule() == r["choice"]
     assert all(ms > 0 for ms in r["backward_ms"].values()) and len(r["backward_ms"]) == 3
-    r3 = autotune.tune_system(systems[3], reps=1, warmup=1)          # a multi-column layout: two schedules
+    r3 = autotune.tune_system(systems[4], reps=1, warmup=1)          # a multi-column layout: two schedules
     assert r3["choice"] in ("one_wave", "two_waves") and list(r3["backward_ms"]) == ["one_wave", "two_waves"]
     b = qoc.Batch(max_contexts=12, max_items=4096)
     rb = autotune.tune_batch(b, systems, reps=2)
