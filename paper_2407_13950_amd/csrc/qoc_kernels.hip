@@ -1818,10 +1818,13 @@ __global__ __launch_bounds__(128) void k_backward_xw(DevSys s, int nitems) {
 // has steps and ends every iteration with the block barrier, outside the role branches.
 // A record of step k is rewritten (for step k-2) only in the iteration after the one in
 // which wavefront 2 read it, i.e. after a barrier.
+constexpr int kX3Steps = 2;                         // steps per block barrier (a power of two)
+
 template <typename T, int Q, int L, int LD, bool HOP>
 __device__ __forceinline__ void backward_item_x3(const DevSys &s, int m, int cg, T *red, T *xb, T *zb, T *yb) {
   using G = Geo<T, Q, L, LD>;
   constexpr int RS = 64 * 2 * G::EPL;               // elements of one step's record
+  constexpr int B = kX3Steps;                       // steps per barrier
   static_assert(2 * G::EPL <= 8, "a step record exceeds its LDS slot (64 lanes x 8 elements)");
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // 0: state, 1: adjoint, 2: inner products
   const int item = m * s.ncg_b + cg;
@@ -1839,45 +1842,59 @@ __device__ __forceinline__ void backward_item_x3(const DevSys &s, int m, int cg,
   T *ser = reinterpret_cast<T *>(s.series) + (size_t)item * s.maxlen * 2 * Q;
   T *own = (wv == 0 ? zb : yb) + roff;
   CkptPos cp(s, k0, k1);
-  for (long long k = k1 - 1; k >= k0 - 1; --k) {
-    if (wv < 2 && k >= k0) {                        // solve step k, leave z or y in record k & 1
-      typename C2<T>::type ccur[Q];
-      load_ctrl<T, Q>(ctrl, k, ccur);
-      Coef<T, Q, L, LD> cf;
-      step_coeffs<T, Q, L, LD>(ln, ccur, cf);
-      T ur[G::EPL], ui[G::EPL], wr[G::EPL], wi[G::EPL];
+  // Iteration b: wavefronts 0 and 1 solve the B steps of block b (steps k1-1-bB .. k1-bB-B),
+  // leaving z or y in record k mod 2B; wavefront 2 takes the inner products of block b-1.
+  // Blocks b and b-1 cover 2B consecutive steps, so their records are distinct; a record of
+  // block b-2 is rewritten only after the barrier that ended wavefront 2's reads of it.
+  const long long nblk = (k1 - k0 + B - 1) / B;
+  for (long long b = 0; b <= nblk; ++b) {
+    if (wv < 2 && b < nblk) {
 #pragma unroll
-      for (int e = 0; e < G::EPL; ++e) {
-        ur[e] = (T)ar[e];
-        ui[e] = (T)ai[e];
-      }
-      solve_increment<T, Q, L, LD, true, HOP>(ln, kit, cf, ur, ui, wr, wi);
-      T *rec = own + (size_t)(k & 1) * RS;
+      for (int i = 0; i < B; ++i) {
+        const long long k = k1 - 1 - b * B - i;
+        if (k < k0) break;                          // uniform: the window's first block may be short
+        typename C2<T>::type ccur[Q];
+        load_ctrl<T, Q>(ctrl, k, ccur);
+        Coef<T, Q, L, LD> cf;
+        step_coeffs<T, Q, L, LD>(ln, ccur, cf);
+        T ur[G::EPL], ui[G::EPL], wr[G::EPL], wi[G::EPL];
 #pragma unroll
-      for (int e = 0; e < G::EPL; ++e) {
-        rec[2 * e] = ur[e] + wr[e];
-        rec[2 * e + 1] = ui[e] + wi[e];
-        ar[e] += 2.0 * (double)wr[e];
-        ai[e] += 2.0 * (double)wi[e];
+        for (int e = 0; e < G::EPL; ++e) {
+          ur[e] = (T)ar[e];
+          ui[e] = (T)ai[e];
+        }
+        solve_increment<T, Q, L, LD, true, HOP>(ln, kit, cf, ur, ui, wr, wi);
+        T *rec = own + (size_t)(k & (2 * B - 1)) * RS;
+#pragma unroll
+        for (int e = 0; e < G::EPL; ++e) {
+          rec[2 * e] = ur[e] + wr[e];
+          rec[2 * e + 1] = ui[e] + wi[e];
+          ar[e] += 2.0 * (double)wr[e];
+          ai[e] += 2.0 * (double)wi[e];
+        }
+        ckpt_step<T, Q, L, LD>(s, m, ln, wv == 0, cp, ar, ai);
       }
-      ckpt_step<T, Q, L, LD>(s, m, ln, wv == 0, cp, ar, ai);
     }
-    if (wv == 2 && k < k1 - 1) {                    // inner products of step k + 1 (records of the last iteration)
-      const long long kp = k + 1;
-      const T *zrec = zb + (size_t)(kp & 1) * RS + roff;
-      const T *yrec = yb + (size_t)(kp & 1) * RS + roff;
-      T zr[G::EPL], zi[G::EPL], yr[G::EPL], yi[G::EPL];
+    if (wv == 2 && b > 0) {                         // inner products of block b - 1
 #pragma unroll
-      for (int e = 0; e < G::EPL; ++e) {
-        zr[e] = zrec[2 * e];
-        zi[e] = zrec[2 * e + 1];
-        yr[e] = yrec[2 * e];
-        yi[e] = yrec[2 * e + 1];
+      for (int i = 0; i < B; ++i) {
+        const long long kp = k1 - 1 - (b - 1) * B - i;
+        if (kp < k0) break;
+        const T *zrec = zb + (size_t)(kp & (2 * B - 1)) * RS + roff;
+        const T *yrec = yb + (size_t)(kp & (2 * B - 1)) * RS + roff;
+        T zr[G::EPL], zi[G::EPL], yr[G::EPL], yi[G::EPL];
+#pragma unroll
+        for (int e = 0; e < G::EPL; ++e) {
+          zr[e] = zrec[2 * e];
+          zi[e] = zrec[2 * e + 1];
+          yr[e] = yrec[2 * e];
+          yi[e] = yrec[2 * e + 1];
+        }
+        T s1[Q], s2[Q];
+        inner_register_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
+        inner_lane_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
+        series_put<T, Q>(red, ser, ln.lane, (int)(kp - k0), (int)(k1 - k0), s1, s2);
       }
-      T s1[Q], s2[Q];
-      inner_register_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
-      inner_lane_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
-      series_put<T, Q>(red, ser, ln.lane, (int)(kp - k0), (int)(k1 - k0), s1, s2);
     }
     __syncthreads();                                // every wavefront, every iteration
   }
@@ -1887,10 +1904,12 @@ __device__ __forceinline__ void backward_item_x3(const DevSys &s, int m, int cg,
   for (int e = 0; e < G::EPL; ++e) l0[ln.row(e)] = double2{ar[e], ai[e]};
 }
 
-// Per block: three exchange buffers, the double-buffered z and y records, and
+// Per block: three exchange buffers, the z and y records of 2 kX3Steps steps each, and
 // wavefront 2's series buffer.
 template <typename T, bool HOP>
-constexpr int x3_lds_elems() { return 3 * (xchg_bytes<T, HOP>() / (int)sizeof(T)) + 4 * 64 * 8 + red_elems<T>(); }
+constexpr int x3_lds_elems() {
+  return 3 * (xchg_bytes<T, HOP>() / (int)sizeof(T)) + 2 * (2 * kX3Steps) * 64 * 8 + red_elems<T>();
+}
 
 template <typename T, int Q, int L, int LD, bool HOP>
 __global__ __launch_bounds__(192) void k_backward_x3(DevSys s, int nitems) {
@@ -1900,8 +1919,8 @@ __global__ __launch_bounds__(192) void k_backward_x3(DevSys s, int nitems) {
   constexpr int XE = xchg_bytes<T, HOP>() / (int)sizeof(T);
   T *xb = lds + (threadIdx.x >> 6) * XE;
   T *zb = lds + 3 * XE;
-  T *yb = zb + 2 * 64 * 8;
-  T *red = yb + 2 * 64 * 8;
+  T *yb = zb + 2 * kX3Steps * 64 * 8;
+  T *red = yb + 2 * kX3Steps * 64 * 8;
   xchg_clear<T, HOP>(xb);
   backward_item_x3<T, Q, L, LD, HOP>(s, item / s.ncg_b, item % s.ncg_b, red, xb, zb, yb);
 }
@@ -2300,8 +2319,8 @@ __global__ __launch_bounds__(192) void k_backward_x3_batch(const DevSys *sys, co
   constexpr int XE = xchg_bytes<T, true>() / (int)sizeof(T);
   T *xb = lds + (threadIdx.x >> 6) * XE;
   T *zb = lds + 3 * XE;
-  T *yb = zb + 2 * 64 * 8;
-  T *red = yb + 2 * 64 * 8;
+  T *yb = zb + 2 * kX3Steps * 64 * 8;
+  T *red = yb + 2 * kX3Steps * 64 * 8;
   xchg_clear<T, true>(xb);
   const int4 it = items[blockIdx.x];
   const DevSys s = sys[it.x];
