@@ -1317,6 +1317,10 @@ __device__ __forceinline__ void inner_lane_digits(const Lane<T, Q, L, LD> &ln, c
 
 // ---------------------------------------------------------------------------- backward sweep
 
+// Steps per block barrier of the backward schedules that hand step records between
+// wavefronts (a power of two).
+constexpr int kX3Steps = 2;
+
 // Per-step inner products are reduced over the wavefront's 64 lanes through LDS:
 // every step each lane stores its 2q partial sums (propagation precision); every RB steps
 // lane i sums, in FP64 and in lane order, the 64 partials of one (step, value)
@@ -1724,53 +1728,67 @@ __device__ __forceinline__ void backward_item_sx(const DevSys &s, int m, int cg,
   CkptPos cp(s, k0, k1);
   typename C2<T>::type cnext[Q];
   if (wv == 0) load_ctrl<T, Q>(ctrl, k1 - 1, cnext);
-  for (long long k = k1 - 1; k >= k0 - 1; --k) {
-    if (wv == 0 && k >= k0) {                       // solve step k, leave z or y in record k & 1
-      typename C2<T>::type ccur[Q];
+  // Iteration b: wavefront 0 solves the B steps of block b, leaving each step's record in
+  // slot k mod 2B; wavefront 1 takes the inner products of block b-1 (slot reuse as in
+  // backward_item_x3).
+  constexpr int B = kX3Steps;
+  const long long nblk = (k1 - k0 + B - 1) / B;
+  for (long long b = 0; b <= nblk; ++b) {
+    if (wv == 0 && b < nblk) {
 #pragma unroll
-      for (int j = 0; j < Q; ++j) ccur[j] = cnext[j];
-      load_ctrl<T, Q>(ctrl, k > k0 ? k - 1 : k, cnext);
-      Coef<T, Q, L, LD> cf;
-      step_coeffs<T, Q, L, LD>(ln, ccur, cf);
-      T ur[G::EPL], ui[G::EPL], wr[G::EPL], wi[G::EPL];
+      for (int i = 0; i < B; ++i) {
+        const long long k = k1 - 1 - b * B - i;
+        if (k < k0) break;                          // uniform: the window's first block may be short
+        typename C2<T>::type ccur[Q];
 #pragma unroll
-      for (int e = 0; e < G::EPL; ++e) {
-        ur[e] = (T)ar[e];
-        ui[e] = (T)ai[e];
+        for (int j = 0; j < Q; ++j) ccur[j] = cnext[j];
+        load_ctrl<T, Q>(ctrl, k > k0 ? k - 1 : k, cnext);
+        Coef<T, Q, L, LD> cf;
+        step_coeffs<T, Q, L, LD>(ln, ccur, cf);
+        T ur[G::EPL], ui[G::EPL], wr[G::EPL], wi[G::EPL];
+#pragma unroll
+        for (int e = 0; e < G::EPL; ++e) {
+          ur[e] = (T)ar[e];
+          ui[e] = (T)ai[e];
+        }
+        solve_increment<T, Q, L, LD, true, HOP>(ln, kit, cf, ur, ui, wr, wi);
+        T *rec = rb + (size_t)(k & (2 * B - 1)) * RS + ln.lane * 2 * G::EPL;
+#pragma unroll
+        for (int e = 0; e < G::EPL; ++e) {
+          rec[2 * e] = ur[e] + wr[e];
+          rec[2 * e + 1] = ui[e] + wi[e];
+          ar[e] += 2.0 * (double)wr[e];
+          ai[e] += 2.0 * (double)wi[e];
+        }
+        ckpt_step<T, Q, L, LD>(s, m, ln, !adj, cp, ar, ai);
       }
-      solve_increment<T, Q, L, LD, true, HOP>(ln, kit, cf, ur, ui, wr, wi);
-      T *rec = rb + (size_t)(k & 1) * RS + ln.lane * 2 * G::EPL;
-#pragma unroll
-      for (int e = 0; e < G::EPL; ++e) {
-        rec[2 * e] = ur[e] + wr[e];
-        rec[2 * e + 1] = ui[e] + wi[e];
-        ar[e] += 2.0 * (double)wr[e];
-        ai[e] += 2.0 * (double)wi[e];
-      }
-      ckpt_step<T, Q, L, LD>(s, m, ln, !adj, cp, ar, ai);
     }
-    if (wv == 1 && k < k1 - 1) {                    // inner products of step k + 1
-      const long long kp = k + 1;
-      const T *base = rb + (size_t)(kp & 1) * RS;
-      const T *zrec = base + (ln.lane & 31) * 2 * G::EPL;
-      const T *yrec = base + ((ln.lane & 31) + 32) * 2 * G::EPL;
-      T zr[G::EPL], zi[G::EPL], yr[G::EPL], yi[G::EPL];
+    if (wv == 1 && b > 0) {                         // inner products of block b - 1
 #pragma unroll
-      for (int e = 0; e < G::EPL; ++e) {
-        zr[e] = zrec[2 * e];
-        zi[e] = zrec[2 * e + 1];
-        yr[e] = yrec[2 * e];
-        yi[e] = yrec[2 * e + 1];
-      }
-      T s1[Q], s2[Q];
-      inner_register_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
-      inner_lane_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
+      for (int i = 0; i < B; ++i) {
+        const long long kp = k1 - 1 - (b - 1) * B - i;
+        if (kp < k0) break;
+        const T *base = rb + (size_t)(kp & (2 * B - 1)) * RS;
+        const T *zrec = base + (ln.lane & 31) * 2 * G::EPL;
+        const T *yrec = base + ((ln.lane & 31) + 32) * 2 * G::EPL;
+        T zr[G::EPL], zi[G::EPL], yr[G::EPL], yi[G::EPL];
 #pragma unroll
-      for (int j = 0; j < Q; ++j) {                 // lanes 32..63 repeat lanes 0..31: count them once
-        s1[j] = adj ? (T)0 : s1[j];
-        s2[j] = adj ? (T)0 : s2[j];
+        for (int e = 0; e < G::EPL; ++e) {
+          zr[e] = zrec[2 * e];
+          zi[e] = zrec[2 * e + 1];
+          yr[e] = yrec[2 * e];
+          yi[e] = yrec[2 * e + 1];
+        }
+        T s1[Q], s2[Q];
+        inner_register_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
+        inner_lane_digits<T, Q, L, LD>(ln, zr, zi, yr, yi, s1, s2);
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {               // lanes 32..63 repeat lanes 0..31: count them once
+          s1[j] = adj ? (T)0 : s1[j];
+          s2[j] = adj ? (T)0 : s2[j];
+        }
+        series_put<T, Q>(red, ser, ln.lane, (int)(kp - k0), (int)(k1 - k0), s1, s2);
       }
-      series_put<T, Q>(red, ser, ln.lane, (int)(kp - k0), (int)(k1 - k0), s1, s2);
     }
     __syncthreads();                                // every wavefront, every iteration
   }
@@ -1780,10 +1798,13 @@ __device__ __forceinline__ void backward_item_sx(const DevSys &s, int m, int cg,
   for (int e = 0; e < G::EPL; ++e) l0[ln.row(e)] = double2{ar[e], ai[e]};
 }
 
-// Per block: wavefront 0's and wavefront 1's exchange buffers, the double-buffered z
-// record, and wavefront 1's series buffer.
+// Per block: wavefront 0's and wavefront 1's exchange buffers, the step records (2 kX3Steps
+// slots: the split layouts' blocks of steps; the one-column form uses two), and wavefront 1's
+// series buffer.
 template <typename T, bool HOP>
-constexpr int xw_lds_elems() { return 2 * (xchg_bytes<T, HOP>() / (int)sizeof(T)) + 2 * 64 * 8 + red_elems<T>(); }
+constexpr int xw_lds_elems() {
+  return 2 * (xchg_bytes<T, HOP>() / (int)sizeof(T)) + 2 * kX3Steps * 64 * 8 + red_elems<T>();
+}
 
 // Two wavefronts per item: state and adjoint for one-column layouts, solves and inner
 // products for layouts with two or more columns per wavefront.
@@ -1803,7 +1824,7 @@ __global__ __launch_bounds__(128) void k_backward_xw(DevSys s, int nitems) {
   constexpr int XE = xchg_bytes<T, HOP>() / (int)sizeof(T);
   T *xb = lds + (threadIdx.x >> 6) * XE;
   T *zb = lds + 2 * XE;
-  T *red = zb + 2 * 64 * 8;
+  T *red = zb + 2 * kX3Steps * 64 * 8;
   xchg_clear<T, HOP>(xb);
   xw_item<T, Q, L, LD, HOP>(s, item / s.ncg_b, item % s.ncg_b, red, xb, zb);
 }
@@ -1818,8 +1839,6 @@ __global__ __launch_bounds__(128) void k_backward_xw(DevSys s, int nitems) {
 // has steps and ends every iteration with the block barrier, outside the role branches.
 // A record of step k is rewritten (for step k-2) only in the iteration after the one in
 // which wavefront 2 read it, i.e. after a barrier.
-constexpr int kX3Steps = 2;                         // steps per block barrier (a power of two)
-
 template <typename T, int Q, int L, int LD, bool HOP>
 __device__ __forceinline__ void backward_item_x3(const DevSys &s, int m, int cg, T *red, T *xb, T *zb, T *yb) {
   using G = Geo<T, Q, L, LD>;
@@ -2299,7 +2318,7 @@ __global__ __launch_bounds__(128) void k_backward_xw_batch(const DevSys *sys, co
   constexpr int XE = xchg_bytes<T, true>() / (int)sizeof(T);
   T *xb = lds + (threadIdx.x >> 6) * XE;
   T *zb = lds + 2 * XE;
-  T *red = zb + 2 * 64 * 8;
+  T *red = zb + 2 * kX3Steps * 64 * 8;
   xchg_clear<T, true>(xb);
   const int4 it = items[blockIdx.x];
   const DevSys s = sys[it.x];
