@@ -213,3 +213,19 @@ def test_tuner_choices_are_valid_and_keep_bit_identity():
     for s in systems:
         s.close()
     b.close()
+
+
+@pytest.mark.parametrize("q,L,sched", [(4, 4, "three_waves"), (4, 4, "two_waves"), (3, 4, "three_waves"),
+                                        (2, 3, "two_waves"), (3, 3, "two_waves")])
+def test_odd_window_lengths_with_two_step_blocks(q, L, sched):
+    """Windows of odd length (203 steps over 4 windows: 50, 51, 51, 51) with checkpoints every 7
+    steps: the schedules that hand step records between wavefronts work in blocks of two steps,
+    so each window's last block is a single step."""
+    w, alpha, W = PG.small_case(q, L, 203, 4, seed=9, ckpt=7)
+    P0, t0, ga0, gW0 = O.gradient(w, alpha, W)
+    for prec in ("fp32", "fp64"):
+        P, t, ga, gW = PG.run_gpu(w, alpha, W, prec, backward_schedule=sched)
+        tol_P, tol_g = TOL[prec]
+        g = grad_rel(ga, gW, ga0, gW0)
+        print(f"{w.name} {prec} {sched}: P rel {abs(P - P0) / abs(P0):.2e}  grad rel-L2 {g:.2e}", flush=True)
+        assert abs(P - P0) <= tol_P * abs(P0) and g <= tol_g
