@@ -48,15 +48,27 @@ def algorithmic_flops(w, kit):
     return fwd * units, bwd * units
 
 
+# The files that decide the propagation kernels' code: their sources and the build flags.
+KERNEL_SOURCES = ("paper_2407_13950_amd/csrc/qoc_kernels.hip", "paper_2407_13950_amd/csrc/qoc_backward_unit.hip",
+                  "paper_2407_13950_amd/build.py")
+
+
+def kernel_sources_sha():
+    """sha256 over KERNEL_SOURCES, read in that order (the key of the committed profiles)."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, rel), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE runs,
-    or None when the kernel source has changed since they were taken."""
-    import hashlib
+    or None when the kernels' sources or build flags have changed since they were taken."""
     path = os.path.join(ROOT, "profiles", "traffic_k_backward_q4L4.json")
-    src = os.path.join(ROOT, "paper_2407_13950_amd", "csrc", "qoc_kernels.hip")
     try:
         rec = json.load(open(path))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = kernel_sources_sha()
     except OSError:
         return None
     if rec.get("source_sha256") != sha or rec.get("kernel") != kernel:

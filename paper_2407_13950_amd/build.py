@@ -9,7 +9,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqoc.so")
-SOURCES = ["qoc_kernels.hip", "qoc_opt_kernels.hip", "qoc_api.cpp", "qoc_opt.cpp"]
+SOURCES = ["qoc_kernels.hip", "qoc_backward_unit.hip", "qoc_opt_kernels.hip", "qoc_api.cpp", "qoc_opt.cpp"]
+# Per-source device flags: the 4-qubit FP32 backward sweep is scheduled for instruction-level
+# parallelism (qoc_backward_unit.hip says why).
+EXTRA = {"qoc_backward_unit.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are switched off for all device code.
@@ -24,7 +27,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
-        cmd = [HIPCC, *COMMON, *DEVICE_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *COMMON, *DEVICE_FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
             cmd = [HIPCC, *COMMON, "-x", "hip", *DEVICE_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:

@@ -43,7 +43,11 @@
 namespace qoc {
 namespace {
 
-constexpr int cipow(int b, int e) { return e <= 0 ? 1 : b * cipow(b, e - 1); }
+constexpr int cipow(int b, int e) {
+  int r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
 constexpr int cpow2(int x) { return x <= 1 ? 1 : 2 * cpow2((x + 1) / 2); }
 
 template <typename T> struct C2 { using type = float2; };
@@ -2226,6 +2230,15 @@ __global__ __launch_bounds__(256) void k_small_batch(const DevSys *sys, const in
 
 // ---------------------------------------------------------------------------- dispatch
 
+}  // namespace
+// The FP32 one-wavefront backward sweep of the 4-qubit 4-level layout (no dipole terms) lives
+// in a compilation unit of its own (qoc_backward_unit.hip, which includes this file with
+// QOC_BACKWARD_UNIT defined): the build gives that unit the instruction scheduler's ILP
+// strategy, which shortens this kernel and lengthens or spills others.
+void (*backward_q4l4_fp32())(DevSys, int);
+namespace {
+
+#ifndef QOC_BACKWARD_UNIT
 struct Kernels {
   void (*fwd)(DevSys, double *, double *, int);
   void (*roll)(DevSys, double *, double *, int);
@@ -2238,8 +2251,10 @@ template <typename T, int Q, int L, int LD, bool HOP>
 Kernels make() {
   void (*xw)(DevSys, int) = k_backward_xw<T, Q, L, LD, HOP>, (*x3)(DevSys, int) = nullptr;
   if constexpr (Geo<T, Q, L, LD>::CPW == 1) x3 = k_backward_x3<T, Q, L, LD, HOP>;
-  return Kernels{k_forward<T, Q, L, LD, false, HOP>, k_forward<T, Q, L, LD, true, HOP>, k_backward<T, Q, L, LD, HOP>,
-                 xw, x3};
+  void (*bwd)(DevSys, int) = nullptr;
+  if constexpr (sizeof(T) == 4 && Q == 4 && L == 4 && LD == 3 && !HOP) bwd = backward_q4l4_fp32();
+  else bwd = k_backward<T, Q, L, LD, HOP>;
+  return Kernels{k_forward<T, Q, L, LD, false, HOP>, k_forward<T, Q, L, LD, true, HOP>, bwd, xw, x3};
 }
 
 // (q, L) -> lane digits, chosen so that each lane holds at most four entries
@@ -2534,5 +2549,13 @@ int launch_phase(const DevSys &s, int phase, hipStream_t st, double *Wout, doubl
 int launch_batch_phase(const BatchPlan &p, int phase, hipStream_t st) {
   return p.fp64 ? batch_phase_T<double>(p, phase, st) : batch_phase_T<float>(p, phase, st);
 }
+
+#else   // QOC_BACKWARD_UNIT
+
+}  // namespace
+
+void (*backward_q4l4_fp32())(DevSys, int) { return k_backward<float, 4, 4, 3, false>; }
+
+#endif  // QOC_BACKWARD_UNIT
 
 }  // namespace qoc

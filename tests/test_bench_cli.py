@@ -35,7 +35,9 @@ def test_traffic_record_matches_only_its_kernel_and_source(tmp_path, monkeypatch
     rec = json.load(open(os.path.join(ROOT, "profiles", "traffic_k_backward_q4L4.json")))
     got = bench.measured_traffic(rec["kernel"])
     import hashlib
-    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2407_13950_amd", "csrc", "qoc_kernels.hip"), "rb")
-                         .read()).hexdigest()
+    h = hashlib.sha256()    # the kernels' sources and the build flags, in this order
+    for rel in (("csrc", "qoc_kernels.hip"), ("csrc", "qoc_backward_unit.hip"), ("build.py",)):
+        h.update(open(os.path.join(ROOT, "paper_2407_13950_amd", *rel), "rb").read())
+    sha = h.hexdigest()
     assert (got == rec["bytes_per_launch"]) == (sha == rec["source_sha256"])
     assert bench.measured_traffic("k_backward_x3<float, 4, 4, 3, false>") is None
