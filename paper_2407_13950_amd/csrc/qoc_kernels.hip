@@ -1620,10 +1620,13 @@ __device__ __forceinline__ void backward_item(const DevSys &s, int m, int cg, T 
   for (int e = 0; e < G::EPL; ++e) l0[ln.row(e)] = double2{ldr[e], ldi[e]};
 }
 
-// The FP32 dipole variant is held to two waves per SIMD (it would otherwise exceed
-// the 256-register budget by a few registers and run at one).
+// Held to two waves per SIMD (a 256-register budget): the FP32 dipole variant, which would
+// otherwise exceed it by a few registers, and the FP64 variant without dipole terms, which
+// would otherwise take 289 and run one wave per SIMD; at two it keeps 25 values in scratch,
+// reloaded a few times per step, and a 2048-item launch runs in one round instead of two.
 template <typename T, int Q, int L, int LD, bool HOP>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HOP && sizeof(T) == 4 ? 2 : 1)))
+__global__ __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu((HOP && sizeof(T) == 4) || (!HOP && sizeof(T) == 8) ? 2 : 1)))
 void k_backward(DevSys s, int nitems) {
   const int item = xcd_item(blockIdx.x, gridDim.x);
   if (item >= nitems) return;
