@@ -49,7 +49,7 @@ def algorithmic_flops(w, kit):
 
 
 # The files that decide the propagation kernels' code: their sources and the build flags.
-KERNEL_SOURCES = ("paper_2407_13950_amd/csrc/qoc_kernels.hip", "paper_2407_13950_amd/csrc/qoc_backward_unit.hip",
+KERNEL_SOURCES = ("paper_2407_13950_amd/csrc/qoc_kernels.hip", "paper_2407_13950_amd/csrc/qoc_ilp_unit.hip",
                   "paper_2407_13950_amd/build.py")
 
 

@@ -9,10 +9,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqoc.so")
-SOURCES = ["qoc_kernels.hip", "qoc_backward_unit.hip", "qoc_opt_kernels.hip", "qoc_api.cpp", "qoc_opt.cpp"]
-# Per-source device flags: the 4-qubit FP32 backward sweep is scheduled for instruction-level
-# parallelism (qoc_backward_unit.hip says why).
-EXTRA = {"qoc_backward_unit.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
+SOURCES = ["qoc_kernels.hip", "qoc_ilp_unit.hip", "qoc_opt_kernels.hip", "qoc_api.cpp", "qoc_opt.cpp"]
+# Per-source device flags: the kernel instances of qoc_ilp_unit.hip are scheduled for
+# instruction-level parallelism (that file says which and why).
+EXTRA = {"qoc_ilp_unit.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are switched off for all device code.

@@ -2233,33 +2233,6 @@ __global__ __launch_bounds__(256) void k_small_batch(const DevSys *sys, const in
 
 // ---------------------------------------------------------------------------- dispatch
 
-}  // namespace
-// The FP32 one-wavefront backward sweep of the 4-qubit 4-level layout (no dipole terms) lives
-// in a compilation unit of its own (qoc_backward_unit.hip, which includes this file with
-// QOC_BACKWARD_UNIT defined): the build gives that unit the instruction scheduler's ILP
-// strategy, which shortens this kernel and lengthens or spills others.
-void (*backward_q4l4_fp32())(DevSys, int);
-namespace {
-
-#ifndef QOC_BACKWARD_UNIT
-struct Kernels {
-  void (*fwd)(DevSys, double *, double *, int);
-  void (*roll)(DevSys, double *, double *, int);
-  void (*bwd)(DevSys, int);
-  void (*bwd_xw)(DevSys, int);     // two wavefronts per item
-  void (*bwd_x3)(DevSys, int);     // three wavefronts per item (one-column layouts only)
-};
-
-template <typename T, int Q, int L, int LD, bool HOP>
-Kernels make() {
-  void (*xw)(DevSys, int) = k_backward_xw<T, Q, L, LD, HOP>, (*x3)(DevSys, int) = nullptr;
-  if constexpr (Geo<T, Q, L, LD>::CPW == 1) x3 = k_backward_x3<T, Q, L, LD, HOP>;
-  void (*bwd)(DevSys, int) = nullptr;
-  if constexpr (sizeof(T) == 4 && Q == 4 && L == 4 && LD == 3 && !HOP) bwd = backward_q4l4_fp32();
-  else bwd = k_backward<T, Q, L, LD, HOP>;
-  return Kernels{k_forward<T, Q, L, LD, false, HOP>, k_forward<T, Q, L, LD, true, HOP>, bwd, xw, x3};
-}
-
 // (q, L) -> lane digits, chosen so that each lane holds at most four entries
 // per state (the backward sweep keeps about 16 such arrays live).  Two-level
 // systems use two entries per lane: their windows are latency-bound chains (few
@@ -2273,6 +2246,50 @@ Kernels make() {
   X(4, 2, 3) X(4, 3, 3) X(4, 4, 3) \
   X(5, 2, 4) X(6, 2, 5)
 
+enum KernelKind { KK_FWD, KK_BWD, KK_XW, KK_X3 };
+
+// Kernel instances built in a compilation unit of their own (qoc_ilp_unit.hip, which
+// includes this file with QOC_ILP_UNIT defined) that the build gives the instruction
+// scheduler's ILP strategy.  It shortens these (the headline 4-qubit FP32 backward, and the
+// latency-bound sweeps of the 2-qubit 3-level FP64 and 3-qubit 4-level FP32 systems as their
+// default schedules run them) without costing occupancy their launches use; for other kernels
+// it lowers occupancy a launch needs or spills.
+template <typename T, int Q, int L, bool HOP, int KK>
+constexpr bool ilp_held() {
+  if constexpr (HOP) return false;
+  else if constexpr (sizeof(T) == 4 && Q == 4 && L == 4) return KK == KK_BWD;
+  else if constexpr (sizeof(T) == 8 && Q == 2 && L == 3) return KK == KK_FWD || KK == KK_XW;
+  else if constexpr (sizeof(T) == 4 && Q == 3 && L == 4) return KK == KK_FWD || KK == KK_X3;
+  else return false;
+}
+
+}  // namespace
+
+struct Kernels {
+  void (*fwd)(DevSys, double *, double *, int);
+  void (*roll)(DevSys, double *, double *, int);
+  void (*bwd)(DevSys, int);
+  void (*bwd_xw)(DevSys, int);     // two wavefronts per item
+  void (*bwd_x3)(DevSys, int);     // three wavefronts per item (one-column layouts only)
+};
+
+// Fills the fields of *k that the ILP unit holds for (precision, q, L) without dipole terms.
+void ilp_kernels(int fp64, int q, int L, Kernels *k);
+
+namespace {
+
+#ifndef QOC_ILP_UNIT
+// This unit's instances; those the ILP unit holds are left null for ilp_kernels().
+template <typename T, int Q, int L, int LD, bool HOP>
+Kernels make() {
+  Kernels k{nullptr, k_forward<T, Q, L, LD, true, HOP>, nullptr, nullptr, nullptr};
+  if constexpr (!ilp_held<T, Q, L, HOP, KK_FWD>()) k.fwd = k_forward<T, Q, L, LD, false, HOP>;
+  if constexpr (!ilp_held<T, Q, L, HOP, KK_BWD>()) k.bwd = k_backward<T, Q, L, LD, HOP>;
+  if constexpr (!ilp_held<T, Q, L, HOP, KK_XW>()) k.bwd_xw = k_backward_xw<T, Q, L, LD, HOP>;
+  if constexpr (Geo<T, Q, L, LD>::CPW == 1 && !ilp_held<T, Q, L, HOP, KK_X3>()) k.bwd_x3 = k_backward_x3<T, Q, L, LD, HOP>;
+  return k;
+}
+
 // Kernel-instance index: the shape, plus N_SHAPES for the dipole variant.
 #define X(Q_, L_, LD_) SHAPE_##Q_##_##L_,
 enum ShapeId { QOC_SHAPES(X) N_SHAPES };
@@ -2282,7 +2299,10 @@ template <typename T>
 bool lookup(int q, int L, bool hop, Kernels *k, int *ld, int *cpw, int *shape) {
 #define X(Q_, L_, LD_)                                                             \
   if (q == Q_ && L == L_) {                                                        \
-    if (k) *k = hop ? make<T, Q_, L_, LD_, true>() : make<T, Q_, L_, LD_, false>(); \
+    if (k) {                                                                       \
+      *k = hop ? make<T, Q_, L_, LD_, true>() : make<T, Q_, L_, LD_, false>();     \
+      if (!hop) ilp_kernels(sizeof(T) == 8, q, L, k);                              \
+    }                                                                              \
     *ld = LD_;                                                                     \
     *cpw = Geo<T, Q_, L_, LD_>::CPW;                                               \
     if (shape) *shape = SHAPE_##Q_##_##L_ + (hop ? N_SHAPES : 0);                  \
@@ -2553,12 +2573,27 @@ int launch_batch_phase(const BatchPlan &p, int phase, hipStream_t st) {
   return p.fp64 ? batch_phase_T<double>(p, phase, st) : batch_phase_T<float>(p, phase, st);
 }
 
-#else   // QOC_BACKWARD_UNIT
+#else   // QOC_ILP_UNIT
+
+template <typename T, int Q, int L, int LD>
+void ilp_fill(Kernels *k) {
+  if constexpr (ilp_held<T, Q, L, false, KK_FWD>()) k->fwd = k_forward<T, Q, L, LD, false, false>;
+  if constexpr (ilp_held<T, Q, L, false, KK_BWD>()) k->bwd = k_backward<T, Q, L, LD, false>;
+  if constexpr (ilp_held<T, Q, L, false, KK_XW>()) k->bwd_xw = k_backward_xw<T, Q, L, LD, false>;
+  if constexpr (Geo<T, Q, L, LD>::CPW == 1 && ilp_held<T, Q, L, false, KK_X3>()) k->bwd_x3 = k_backward_x3<T, Q, L, LD, false>;
+}
 
 }  // namespace
 
-void (*backward_q4l4_fp32())(DevSys, int) { return k_backward<float, 4, 4, 3, false>; }
+void ilp_kernels(int fp64, int q, int L, Kernels *k) {
+#define X(Q_, L_, LD_)                                             \
+  if (q == Q_ && L == L_) {                                        \
+    if (fp64) ilp_fill<double, Q_, L_, LD_>(k); else ilp_fill<float, Q_, L_, LD_>(k); \
+  }
+  QOC_SHAPES(X)
+#undef X
+}
 
-#endif  // QOC_BACKWARD_UNIT
+#endif  // QOC_ILP_UNIT
 
 }  // namespace qoc

@@ -36,7 +36,7 @@ def test_traffic_record_matches_only_its_kernel_and_source(tmp_path, monkeypatch
     got = bench.measured_traffic(rec["kernel"])
     import hashlib
     h = hashlib.sha256()    # the kernels' sources and the build flags, in this order
-    for rel in (("csrc", "qoc_kernels.hip"), ("csrc", "qoc_backward_unit.hip"), ("build.py",)):
+    for rel in (("csrc", "qoc_kernels.hip"), ("csrc", "qoc_ilp_unit.hip"), ("build.py",)):
         h.update(open(os.path.join(ROOT, "paper_2407_13950_amd", *rel), "rb").read())
     sha = h.hexdigest()
     assert (got == rec["bytes_per_launch"]) == (sha == rec["source_sha256"])
