@@ -2250,13 +2250,14 @@ enum KernelKind { KK_FWD, KK_BWD, KK_XW, KK_X3 };
 
 // Kernel instances built in a compilation unit of their own (qoc_ilp_unit.hip, which
 // includes this file with QOC_ILP_UNIT defined) that the build gives the instruction
-// scheduler's ILP strategy.  It shortens these (the headline 4-qubit FP32 backward, and the
-// latency-bound sweeps of the 2-qubit 3-level FP64 and 3-qubit 4-level FP32 systems as their
-// default schedules run them) without costing occupancy their launches use; for other kernels
-// it lowers occupancy a launch needs or spills.
+// scheduler's ILP strategy.  It shortens these (the headline 4-qubit FP32 backward, the FP32
+// forward of the 4-qubit system with dipole terms, and the latency-bound sweeps of the 2-qubit
+// 3-level FP64 and 3-qubit 4-level FP32 systems as their default schedules run them) without
+// costing occupancy their launches use; for other kernels it lowers occupancy a launch needs or
+// spills (the 4-qubit FP32 backward with dipole terms among them).
 template <typename T, int Q, int L, bool HOP, int KK>
 constexpr bool ilp_held() {
-  if constexpr (HOP) return false;
+  if constexpr (HOP) return sizeof(T) == 4 && Q == 4 && L == 4 && KK == KK_FWD;
   else if constexpr (sizeof(T) == 4 && Q == 4 && L == 4) return KK == KK_BWD;
   else if constexpr (sizeof(T) == 8 && Q == 2 && L == 3) return KK == KK_FWD || KK == KK_XW;
   else if constexpr (sizeof(T) == 4 && Q == 3 && L == 4) return KK == KK_FWD || KK == KK_X3;
@@ -2273,8 +2274,8 @@ struct Kernels {
   void (*bwd_x3)(DevSys, int);     // three wavefronts per item (one-column layouts only)
 };
 
-// Fills the fields of *k that the ILP unit holds for (precision, q, L) without dipole terms.
-void ilp_kernels(int fp64, int q, int L, Kernels *k);
+// Fills the fields of *k that the ILP unit holds for (precision, q, L, dipole terms).
+void ilp_kernels(int fp64, int q, int L, int hop, Kernels *k);
 
 namespace {
 
@@ -2301,7 +2302,7 @@ bool lookup(int q, int L, bool hop, Kernels *k, int *ld, int *cpw, int *shape) {
   if (q == Q_ && L == L_) {                                                        \
     if (k) {                                                                       \
       *k = hop ? make<T, Q_, L_, LD_, true>() : make<T, Q_, L_, LD_, false>();     \
-      if (!hop) ilp_kernels(sizeof(T) == 8, q, L, k);                              \
+      ilp_kernels(sizeof(T) == 8, q, L, hop, k);                                   \
     }                                                                              \
     *ld = LD_;                                                                     \
     *cpw = Geo<T, Q_, L_, LD_>::CPW;                                               \
@@ -2575,20 +2576,21 @@ int launch_batch_phase(const BatchPlan &p, int phase, hipStream_t st) {
 
 #else   // QOC_ILP_UNIT
 
-template <typename T, int Q, int L, int LD>
+template <typename T, int Q, int L, int LD, bool HOP>
 void ilp_fill(Kernels *k) {
-  if constexpr (ilp_held<T, Q, L, false, KK_FWD>()) k->fwd = k_forward<T, Q, L, LD, false, false>;
-  if constexpr (ilp_held<T, Q, L, false, KK_BWD>()) k->bwd = k_backward<T, Q, L, LD, false>;
-  if constexpr (ilp_held<T, Q, L, false, KK_XW>()) k->bwd_xw = k_backward_xw<T, Q, L, LD, false>;
-  if constexpr (Geo<T, Q, L, LD>::CPW == 1 && ilp_held<T, Q, L, false, KK_X3>()) k->bwd_x3 = k_backward_x3<T, Q, L, LD, false>;
+  if constexpr (ilp_held<T, Q, L, HOP, KK_FWD>()) k->fwd = k_forward<T, Q, L, LD, false, HOP>;
+  if constexpr (ilp_held<T, Q, L, HOP, KK_BWD>()) k->bwd = k_backward<T, Q, L, LD, HOP>;
+  if constexpr (ilp_held<T, Q, L, HOP, KK_XW>()) k->bwd_xw = k_backward_xw<T, Q, L, LD, HOP>;
+  if constexpr (Geo<T, Q, L, LD>::CPW == 1 && ilp_held<T, Q, L, HOP, KK_X3>()) k->bwd_x3 = k_backward_x3<T, Q, L, LD, HOP>;
 }
 
 }  // namespace
 
-void ilp_kernels(int fp64, int q, int L, Kernels *k) {
-#define X(Q_, L_, LD_)                                             \
-  if (q == Q_ && L == L_) {                                        \
-    if (fp64) ilp_fill<double, Q_, L_, LD_>(k); else ilp_fill<float, Q_, L_, LD_>(k); \
+void ilp_kernels(int fp64, int q, int L, int hop, Kernels *k) {
+#define X(Q_, L_, LD_)                                                                   \
+  if (q == Q_ && L == L_) {                                                              \
+    if (fp64) hop ? ilp_fill<double, Q_, L_, LD_, true>(k) : ilp_fill<double, Q_, L_, LD_, false>(k); \
+    else hop ? ilp_fill<float, Q_, L_, LD_, true>(k) : ilp_fill<float, Q_, L_, LD_, false>(k);       \
   }
   QOC_SHAPES(X)
 #undef X
